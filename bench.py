@@ -1,0 +1,140 @@
+#!/usr/bin/env python3
+"""Benchmark of the IMEX PD-ARS radiation step on one MI355X.
+
+Workload (a "step" is one full PD-ARS radiation step: both fused stage kernels,
+transport + local implicit source, over the whole grid): the 3-D 128^3 FP64
+static mixed-regime grid (periodic; log-normal tau_cell in 1e-3..1e3; T = 1 +
+0.1 GRF(8); T_rad offset +/-20 %; chat = c/100), inputs synthetic and resident in
+HBM before the timed region. Prints one JSON line.
+
+  value     = cells * steps / wall time of the timed rhd_step call (cell-updates/s)
+  roofline  = algorithmic HBM bytes of the dominant stage kernel per launch over its
+              average duration (hipEvents on the library's stream, same timed region)
+  cpu_baseline = the CPU oracle (OpenMP over cells) on a bounded sample of the
+              same workload (rank 0, N = 1)
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes_per_cell(ndim):
+    """Compulsory float64 HBM traffic per cell of each stage kernel.
+    Stage 1 reads y^n (nvar) + rho + kappa and writes y^{n+1/2} (nvar);
+    stage 2 reads y^{n+1/2} (nvar) + y^n (nvar) + rho + kappa and writes y^{n+1}."""
+    nvar = 2 + 2 * ndim
+    return 8 * (nvar + 2 + nvar), 8 * (2 * nvar + 2 + nvar)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--cpu-steps", type=int, default=8,
+                    help="oracle steps in the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision line item")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs (halo exchange over "
+              "xGMI) are a design, not part of this build. Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_08247_amd import rhd, workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.config2(precision=args.precision)
+    print(f"[bench] workload {w.name} cells={w.ncells} steps={args.steps} warmup={args.warmup}",
+          file=sys.stderr, flush=True)
+
+    def to(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    rho, kap = to(w.rho), to(w.kappa_P)
+    y = to(w.y0)
+    S = rhd.Solver(w.params, rho, kap, None, 0, dev)
+    if args.warmup > 0:
+        S.step(y, w.dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms1, ms2 = S.step_timed(y, w.dt, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cells = w.ncells
+    value = cells * args.steps / wall
+    b1, b2 = stage_bytes_per_cell(w.ndim)
+    t1, t2 = ms1 / args.steps * 1e-3, ms2 / args.steps * 1e-3
+    if t2 >= t1:
+        kname, kb, kt = "k_stage<3,STAGE2>", b2, t2
+    else:
+        kname, kb, kt = "k_stage<3,STAGE1>", b1, t1
+    achieved = kb * cells / kt / 1e9
+    print(f"[bench] stage1 {t1 * 1e6:.1f} us  stage2 {t2 * 1e6:.1f} us  wall/step "
+          f"{wall / args.steps * 1e6:.1f} us", file=sys.stderr, flush=True)
+
+    extras = {}
+    if not args.no_extras and args.precision == "fp64":
+        wm = W.config2(precision="mixed")
+        ym = to(wm.y0)
+        Sm = rhd.Solver(wm.params, rho, kap, None, 0, dev)
+        Sm.step(ym, wm.dt, max(1, args.warmup))
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        Sm.step(ym, wm.dt, args.steps)
+        torch.cuda.synchronize()
+        wallm = time.perf_counter() - tm
+        extras["mixed_precision"] = {"value": cells * args.steps / wallm,
+                                     "unit": "cell-updates/s", "steps": args.steps,
+                                     "ms_per_step": wallm / args.steps * 1e3}
+
+    cpu = None
+    if args.cpu_steps > 0:
+        import oracle
+        wc = W.config2(precision="fp64")
+        tc = time.perf_counter()
+        _, st, _ = oracle.step(wc.params, wc.y0, wc.rho, wc.kappa_P, None, wc.dt, args.cpu_steps)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": wc.ncells * args.cpu_steps / tcpu, "unit": "cell-updates/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"first {args.cpu_steps} of the 200 steps of the same 128^3 FP64 "
+                         f"workload (OpenMP over cells), {tcpu:.1f} s"}
+
+    line = {
+        "metric": "IMEX RHD cell-updates/s (FP64 step; mixed precision reported alongside)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "3-D 128^3 static mixed-regime grid, periodic, chat = c/100 "
+                               "(configs[1])", "cells": cells, "precision": args.precision,
+                   "steps_per_call": args.steps},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_cell": kb,
+                     "avg_launch_us": kt * 1e6},
+        "cpu_baseline": cpu,
+    }
+    line.update(extras)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

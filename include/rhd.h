@@ -1,0 +1,157 @@
+/*
+ * rhd.h - C ABI of the MI355X radiation step.
+ *
+ * One step is the asymptotically-correct IMEX PD-ARS radiation update of
+ * He, Wibking & Krumholz (2024), "An Asymptotically-Correct Implicit-Explicit
+ * Time Integration Scheme for Finite Volume Radiation-Hydrodynamics":
+ *   stage 1:  y(t) = y^n + dt s(y^n),                 y^{n+1/2} = Src(y(t), theta = 1)
+ *   stage 2:  y(t) = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2}),  y^{n+1} = Src(y(t), theta = 1/2)
+ * (Sec. 3.2, eq. imex1-imex2, PD-ARS tableau with epsilon = 0; stage 2 uses the
+ * stage-1 source increment in place of dt f(y^{n+1/2}), which is the same thing
+ * once stage 1 holds). s is the explicit finite-volume transport of (E, F) in
+ * reduced-speed-of-light form (eq. yrsla): PPM edge states, Levermore M1 or
+ * Eddington closure, HLL flux with the uncorrected wave speed chat sqrt(D_dd)
+ * (Sec. 3.3, Sec. 4.3). Src is the purely local implicit gas-radiation update of
+ * Sec. 3.3 (eq. egupdate-fupdate): inner Newton on (E_gas, R) with residuals
+ * eq. FGFR and R from eq. Rnew, energy recovery from conservation, flux update
+ * eq. numF1 (v_order 1) or eq. numF2 (v_order 2), momentum update, and the outer
+ * iteration over the lagged v and F.
+ *
+ * Conventions for every entry point
+ *  - Array arguments are DEVICE pointers to caller-owned memory (for example
+ *    torch tensors on the same GPU); the library never allocates device memory
+ *    and never frees caller memory. The handle keeps the pointers it is given at
+ *    create; the caller keeps them alive until rhd_destroy.
+ *  - Grids are uniform Cartesian with spacing dx on every axis. Scalar fields are
+ *    float64 arrays [nz][ny][nx] (x fastest). The state is float64
+ *    [nvar][nz][ny][nx] with nvar = 2 + 2*ndim and variables in the order
+ *    (E, F_1..F_ndim, E_gas, (rho v)_1..(rho v)_ndim): lab-frame radiation
+ *    energy density and flux (physical units, not F/(c chat)), gas total energy
+ *    density and momentum density.
+ *  - Work is enqueued on the HIP stream given at create. Calls that return a
+ *    status synchronise that stream once at the end (to read the device error
+ *    word); no call synchronises the device.
+ *  - Errors are returned as rhd_status; nothing is thrown across the ABI.
+ *    A handle is bound to one stream and one device and is not thread-safe.
+ */
+#ifndef RHD_H
+#define RHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rhd_handle rhd_handle; /* opaque, host-side, library-owned */
+
+typedef enum {
+  RHD_OK = 0,
+  RHD_EINVAL = -1,      /* invalid parameter or argument; nothing was launched */
+  RHD_ENEWTON = -2,     /* inner Newton did not converge in newton_maxit iterations in some cell */
+  RHD_ENONPHYS = -3,    /* E <= 0 or internal energy E_gas - |rho v|^2/(2 rho) <= 0 after the update */
+  RHD_EHIP = -4,        /* a HIP runtime call failed (launch, copy, synchronisation) */
+  RHD_EWORKSPACE = -5   /* workspace pointer NULL, misaligned or smaller than rhd_workspace_bytes */
+} rhd_status;
+
+enum { RHD_BC_PERIODIC = 0, RHD_BC_REFLECT = 1 };
+enum { RHD_CLOSURE_M1 = 0, RHD_CLOSURE_EDDINGTON = 1 };
+enum { RHD_FP64 = 0, RHD_MIXED = 1 };
+
+typedef struct {
+  int32_t ndim;          /* 1, 2 or 3 */
+  int32_t closure;       /* RHD_CLOSURE_M1 (Levermore) or RHD_CLOSURE_EDDINGTON (P = E/3 I) */
+  int64_t n[3];          /* cells per axis (nx, ny, nz); axes beyond ndim must be 1 */
+  double dx;             /* cell size, > 0 */
+  double c;              /* speed of light, > 0 */
+  double chat;           /* reduced speed of light, 0 < chat <= c (Sec. 3.2, RSLA) */
+  double gamma;          /* adiabatic index, > 1; c_v = kB_over_mu / (gamma - 1) per unit mass */
+  double a_r;            /* radiation constant: 4 pi B / c = a_r T^4, > 0 */
+  double kB_over_mu;     /* k_B / (mu m_H), > 0 */
+  int32_t bc[3];         /* RHD_BC_PERIODIC or RHD_BC_REFLECT per axis (reflect needs n >= 3) */
+  int32_t v_order;       /* 1: O(v/c) source terms, eq. numF1; 2: O(v^2/c^2), eq. numF2
+                            (order 2 needs kappa_F == kappa_P: pass kappa_F = NULL or kappa_P) */
+  int32_t precision;     /* RHD_FP64, or RHD_MIXED: transport stencil in float32, state,
+                            flux-divergence accumulation and the source in float64 */
+  int32_t newton_maxit;  /* inner Newton iteration cap (>= 1; 50 recommended) */
+  int32_t outer_maxit;   /* outer iteration cap (>= 1; 10 recommended); reaching it is not an error */
+  int32_t reserved;      /* must be 0 */
+  double newton_rtol;    /* Newton stopping tolerance relative to E_gas + (c/chat) E (1e-13 in the paper) */
+  double outer_rtol;     /* outer stopping tolerance on the v- and F-dependent part of R (1e-13) */
+} rhd_params;
+
+/* Bytes of device workspace rhd_create needs for these parameters.
+ * adjoint_segment_len = 0 sizes the forward step only; k > 0 also sizes
+ * rhd_step_adjoint for segments of up to k steps (it stores y^n and y^{n+1/2}
+ * of every step of a segment). Returns 0 for invalid parameters. */
+size_t rhd_workspace_bytes(const rhd_params* p, int32_t adjoint_segment_len);
+
+/* Validate the parameters and bind them, the scalar fields and the workspace
+ * to a new handle.
+ *   rho, kappa_P: device float64 [nz][ny][nx]; density and Planck-mean opacity
+ *     per unit mass (chi_P = chi_E = rho kappa_P, Sec. 2.1 eq. G0-G1, grey).
+ *   kappa_F: flux-mean opacity per unit mass, or NULL (or kappa_P) for kappa_F = kappa_P.
+ *   workspace: device memory of ws_bytes >= rhd_workspace_bytes(p, k), 256-byte
+ *     aligned; owned by the caller, used exclusively by this handle.
+ *   hip_stream: hipStream_t (NULL = default stream) on which all work is enqueued.
+ *   adjoint_segment_len: the k the workspace was sized for (0 = forward only).
+ * On success *out receives the handle; on failure *out is left untouched. */
+rhd_status rhd_create(const rhd_params* p, const double* rho, const double* kappa_P,
+                      const double* kappa_F, void* workspace, size_t ws_bytes,
+                      int32_t adjoint_segment_len, void* hip_stream, rhd_handle** out);
+
+/* Advance state (device float64 [nvar][nz][ny][nx], in/out) by nsteps PD-ARS
+ * steps of size dt > 0 (Sec. 3.2-3.3). Two fused stage kernels per step; no host
+ * synchronisation until the end of the call. On RHD_ENEWTON / RHD_ENONPHYS the
+ * state holds what was computed (every step still ran); rhd_last_error names the
+ * smallest failing cell index. */
+rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps);
+
+/* Reverse-mode derivative of nsteps steps (nsteps <= the handle's
+ * adjoint_segment_len) started from state0 (device, not modified).
+ *   lambda: in: dJ/dy at the end of the segment; out: dJ/dy at its start.
+ *   g_kappa_P, g_kappa_F: device [nz][ny][nx]; dJ/dkappa is ADDED (+=). With
+ *     kappa_F aliasing kappa_P, g_kappa_F may be NULL and both contributions go
+ *     into g_kappa_P.
+ * The forward steps are recomputed from state0 inside the call; each local
+ * implicit solve is differentiated with the implicit function theorem at its
+ * converged state. */
+rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int32_t nsteps,
+                            double* lambda, double* g_kappa_P, double* g_kappa_F);
+
+/* Row-level entry points (same kernels as rhd_step), for testing one part.
+ * rhd_transport: s (device [nvar][...]) = explicit transport of y; the E and F
+ *   rows receive -div(flux) (eq. yrsla), the gas rows 0.
+ * rhd_source: y (in/out) = Src(y, theta dt = tau) in every cell (Sec. 3.3).
+ * rhd_stage1: yh = Src(y + dt s(y), dt) (eq. imex1). */
+rhd_status rhd_transport(rhd_handle* h, const double* y, double* s);
+rhd_status rhd_source(rhd_handle* h, double* y, double tau);
+rhd_status rhd_stage1(rhd_handle* h, const double* y, double* yh, double dt);
+
+/* rhd_step with per-stage kernel timing: hipEvents are recorded on the handle's
+ * stream around every stage launch; on return stage_ms[0] and stage_ms[1] hold
+ * the summed durations (ms) of the stage-1 and stage-2 kernels over the nsteps
+ * steps (HOST array of 2 doubles). Results are identical to rhd_step. */
+rhd_status rhd_step_timed(rhd_handle* h, double* state, double dt, int32_t nsteps,
+                          double* stage_ms);
+
+/* Conserved totals of a state (diagnostics, not part of the timed step):
+ * out[0] = sum(E_gas + (c/chat) E), out[1..ndim] = sum((rho v)_k + F_k/(c chat))
+ * (energy and momentum that the source update conserves exactly, Sec. 3.3).
+ * out is a HOST array of 1 + ndim doubles. */
+rhd_status rhd_conserved_totals(rhd_handle* h, const double* state, double* out);
+
+/* Error details of the last call on h: *cell = smallest failing cell index (or
+ * -1), msg receives a NUL-terminated description (truncated to len). Returns the
+ * status of the last call. */
+rhd_status rhd_last_error(const rhd_handle* h, int64_t* cell, char* msg, size_t len);
+
+/* Release the handle (host memory only; caller memory is untouched). NULL is a no-op. */
+void rhd_destroy(rhd_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RHD_H */

@@ -1,0 +1,52 @@
+"""Build the HIP library librhd.so for gfx950 (in-tree, next to this file).
+
+hipcc compiles the kernels (csrc/*.hip) and the C-ABI host runtime
+(csrc/rhd_api.cpp) into one shared library. Packed-FP32 instructions are
+disabled for all device code.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "librhd.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+SOURCES = ["rhd_forward.hip", "rhd_adjoint.hip", "rhd_api.cpp"]
+
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    "-I", os.path.join(HERE, "..", "include"),
+]
+
+
+def build(verbose=False, extra=()):
+    objs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        if not os.path.exists(path):
+            continue
+        obj = os.path.join(CSRC, src + ".o")
+        cmd = [HIPCC, *FLAGS, *extra, "-c", path, "-o", obj]
+        if src.endswith(".cpp"):
+            cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I",
+                   os.path.join(HERE, "..", "include"), *extra, "-c", path, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", OUT + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(OUT + ".tmp", OUT)
+    for o in objs:
+        os.remove(o)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose=True, extra=sys.argv[1:])

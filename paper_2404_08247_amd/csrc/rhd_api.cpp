@@ -1,0 +1,345 @@
+// Host runtime of the C ABI declared in include/rhd.h: parameter validation,
+// workspace carving, stage-kernel launches on the caller's stream and the
+// device error word. No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rhd.h"
+#include "rhd_internal.hpp"
+
+struct rhd_handle {
+  rhd_params p;
+  rhd::DevParams dp;
+  const double* rho;
+  const double* kP;
+  const double* kF;           // == kP when aliased
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  int adj_len;
+  // carved workspace
+  unsigned long long* err;    // 2 words
+  double* yhalf;              // nvar * N
+  double* partial;            // reduction scratch
+  int partial_blocks;
+  double* adj_base;           // adjoint storage (segment states and adjoint scratch)
+  size_t adj_bytes;
+  // last error
+  rhd_status last;
+  long long last_cell;
+  std::string last_msg;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kPartialBlocks = 1024;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int nvar_of(const rhd_params* p) { return 2 + 2 * p->ndim; }
+
+long long ncells(const rhd_params* p) { return p->n[0] * p->n[1] * p->n[2]; }
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Returns an empty string when valid, else the reason.
+std::string validate(const rhd_params* p) {
+  if (!p) return "params is NULL";
+  if (p->ndim < 1 || p->ndim > 3) return "ndim must be 1, 2 or 3";
+  for (int d = 0; d < 3; ++d) {
+    if (d < p->ndim) {
+      if (p->n[d] < 1) return "n[d] must be >= 1 on active axes";
+      if (p->n[d] > (1LL << 24)) return "n[d] too large";
+      if (p->bc[d] != RHD_BC_PERIODIC && p->bc[d] != RHD_BC_REFLECT) return "bc must be periodic or reflect";
+      if (p->bc[d] == RHD_BC_REFLECT && p->n[d] < 3) return "reflecting axes need n >= 3";
+    } else if (p->n[d] != 1) {
+      return "axes beyond ndim must have n = 1";
+    }
+  }
+  if (ncells(p) > (1LL << 40)) return "grid too large";
+  if (!finite_pos(p->dx)) return "dx must be > 0";
+  if (!finite_pos(p->c)) return "c must be > 0";
+  if (!finite_pos(p->chat) || p->chat > p->c) return "chat must satisfy 0 < chat <= c";
+  if (!std::isfinite(p->gamma) || p->gamma <= 1.0) return "gamma must be > 1";
+  if (!finite_pos(p->a_r)) return "a_r must be > 0";
+  if (!finite_pos(p->kB_over_mu)) return "kB_over_mu must be > 0";
+  if (p->closure != RHD_CLOSURE_M1 && p->closure != RHD_CLOSURE_EDDINGTON) return "unknown closure";
+  if (p->v_order != 1 && p->v_order != 2) return "v_order must be 1 or 2";
+  if (p->precision != RHD_FP64 && p->precision != RHD_MIXED) return "unknown precision";
+  if (p->newton_maxit < 1 || p->newton_maxit > 100000) return "newton_maxit out of range";
+  if (p->outer_maxit < 1 || p->outer_maxit > 100000) return "outer_maxit out of range";
+  if (p->reserved != 0) return "reserved must be 0";
+  if (!(p->newton_rtol > 0.0) || !std::isfinite(p->newton_rtol)) return "newton_rtol must be > 0";
+  if (!(p->outer_rtol >= 0.0) || !std::isfinite(p->outer_rtol)) return "outer_rtol must be >= 0";
+  return "";
+}
+
+struct Layout {
+  size_t err, yhalf, partial, adj, total;
+};
+
+Layout layout(const rhd_params* p, int adj_len) {
+  const size_t N = (size_t)ncells(p);
+  const size_t nv = (size_t)nvar_of(p);
+  Layout L;
+  size_t off = 0;
+  L.err = off;
+  off = align_up(off + 2 * sizeof(unsigned long long));
+  L.yhalf = off;
+  off = align_up(off + nv * N * sizeof(double));
+  L.partial = off;
+  off = align_up(off + (size_t)kPartialBlocks * 4 * sizeof(double));
+  L.adj = off;
+  if (adj_len > 0) {
+    // y^n and y^{n+1/2} of every step of a segment, plus two adjoint vectors,
+    // plus per-face flux adjoints (3 axes x (1 + ndim) components).
+    off = align_up(off + (size_t)(2 * adj_len + 2) * nv * N * sizeof(double));
+    off = align_up(off + (size_t)3 * (1 + p->ndim) * N * sizeof(double));
+  }
+  L.total = off;
+  return L;
+}
+
+rhd::DevParams make_dev(const rhd_params* p, bool alias) {
+  rhd::DevParams d{};
+  d.ndim = p->ndim;
+  d.closure = p->closure;
+  d.v_order = p->v_order;
+  for (int k = 0; k < 3; ++k) {
+    d.bc[k] = p->bc[k];
+    d.n[k] = (int)p->n[k];
+  }
+  d.newton_maxit = p->newton_maxit;
+  d.outer_maxit = p->outer_maxit;
+  d.N = ncells(p);
+  d.dx = p->dx;
+  d.inv_dx = 1.0 / p->dx;
+  d.c = p->c;
+  d.chat = p->chat;
+  d.c_over_chat = p->c / p->chat;
+  d.chat_over_c = p->chat / p->c;
+  d.c_chat = p->c * p->chat;
+  d.inv_c_chat = 1.0 / (p->c * p->chat);
+  d.inv_c2 = 1.0 / (p->c * p->c);
+  d.a_r = p->a_r;
+  d.cv_mass = p->kB_over_mu / (p->gamma - 1.0);
+  d.newton_rtol = p->newton_rtol;
+  d.outer_rtol = p->outer_rtol;
+  d.kF_alias = alias ? 1 : 0;
+  return d;
+}
+
+rhd_status set_err(rhd_handle* h, rhd_status st, long long cell, const std::string& msg) {
+  h->last = st;
+  h->last_cell = cell;
+  h->last_msg = msg;
+  return st;
+}
+
+rhd_status hip_fail(rhd_handle* h, hipError_t e, const char* where) {
+  return set_err(h, RHD_EHIP, -1, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Read the device error word (one synchronisation of the handle's stream).
+rhd_status finish(rhd_handle* h) {
+  unsigned long long w[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(w, h->err, sizeof(w), hipMemcpyDeviceToHost, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync(error word)");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  if (w[1] == 0) return set_err(h, RHD_OK, -1, "");
+  const long long cell = (w[0] == ULLONG_MAX) ? -1 : (long long)w[0];
+  if (w[1] & rhd::ERR_NEWTON)
+    return set_err(h, RHD_ENEWTON, cell, "inner Newton did not converge (smallest failing cell reported)");
+  return set_err(h, RHD_ENONPHYS, cell, "non-physical state: E <= 0 or internal energy <= 0");
+}
+
+bool misaligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % 8) != 0; }
+
+}  // namespace
+
+extern "C" {
+
+size_t rhd_workspace_bytes(const rhd_params* p, int32_t adjoint_segment_len) {
+  if (!validate(p).empty() || adjoint_segment_len < 0) return 0;
+  return layout(p, adjoint_segment_len).total;
+}
+
+rhd_status rhd_create(const rhd_params* p, const double* rho, const double* kappa_P,
+                      const double* kappa_F, void* workspace, size_t ws_bytes,
+                      int32_t adjoint_segment_len, void* hip_stream, rhd_handle** out) {
+  if (!out) return RHD_EINVAL;
+  if (!validate(p).empty()) return RHD_EINVAL;
+  if (!rho || !kappa_P || misaligned(rho) || misaligned(kappa_P) || misaligned(kappa_F))
+    return RHD_EINVAL;
+  if (adjoint_segment_len < 0 || adjoint_segment_len > 1000000) return RHD_EINVAL;
+  const bool alias = (kappa_F == nullptr || kappa_F == kappa_P);
+  if (p->v_order == 2 && !alias) return RHD_EINVAL;
+  const Layout L = layout(p, adjoint_segment_len);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < L.total)
+    return RHD_EWORKSPACE;
+  rhd_handle* h = new (std::nothrow) rhd_handle();
+  if (!h) return RHD_EINVAL;
+  h->p = *p;
+  h->dp = make_dev(p, alias);
+  h->rho = rho;
+  h->kP = kappa_P;
+  h->kF = alias ? kappa_P : kappa_F;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->ws = reinterpret_cast<char*>(workspace);
+  h->ws_bytes = ws_bytes;
+  h->adj_len = adjoint_segment_len;
+  h->err = reinterpret_cast<unsigned long long*>(h->ws + L.err);
+  h->yhalf = reinterpret_cast<double*>(h->ws + L.yhalf);
+  h->partial = reinterpret_cast<double*>(h->ws + L.partial);
+  h->partial_blocks = kPartialBlocks;
+  h->adj_base = reinterpret_cast<double*>(h->ws + L.adj);
+  h->adj_bytes = L.total - L.adj;
+  h->last = RHD_OK;
+  h->last_cell = -1;
+  *out = h;
+  return RHD_OK;
+}
+
+rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps) {
+  if (!h) return RHD_EINVAL;
+  if (!state || misaligned(state) || !std::isfinite(dt) || !(dt > 0.0) || nsteps < 0)
+    return set_err(h, RHD_EINVAL, -1, "invalid state pointer, dt or nsteps");
+  const bool mixed = (h->p.precision == RHD_MIXED);
+  hipError_t e = rhd::launch_reset_err(h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset");
+  for (int n = 0; n < nsteps; ++n) {
+    e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, mixed, state, state, h->yhalf, h->rho, h->kP,
+                          h->kF, dt, h->err, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stage 1 launch");
+    e = rhd::launch_stage(h->dp, rhd::MODE_STAGE2, mixed, h->yhalf, state, state, h->rho, h->kP,
+                          h->kF, dt, h->err, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "stage 2 launch");
+  }
+  return finish(h);
+}
+
+rhd_status rhd_step_timed(rhd_handle* h, double* state, double dt, int32_t nsteps,
+                          double* stage_ms) {
+  if (!h) return RHD_EINVAL;
+  if (!state || !stage_ms || misaligned(state) || !std::isfinite(dt) || !(dt > 0.0) || nsteps < 0)
+    return set_err(h, RHD_EINVAL, -1, "invalid state pointer, dt, nsteps or stage_ms");
+  const bool mixed = (h->p.precision == RHD_MIXED);
+  std::vector<hipEvent_t> ev((size_t)2 * nsteps + 1, nullptr);
+  auto cleanup = [&]() {
+    for (auto& x : ev)
+      if (x) (void)hipEventDestroy(x);
+  };
+  hipError_t e = hipSuccess;
+  for (auto& x : ev) {
+    e = hipEventCreate(&x);
+    if (e != hipSuccess) {
+      cleanup();
+      return hip_fail(h, e, "hipEventCreate");
+    }
+  }
+  e = rhd::launch_reset_err(h->err, h->stream);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], h->stream);
+  for (int n = 0; n < nsteps && e == hipSuccess; ++n) {
+    e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, mixed, state, state, h->yhalf, h->rho, h->kP,
+                          h->kF, dt, h->err, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * n + 1], h->stream);
+    if (e == hipSuccess)
+      e = rhd::launch_stage(h->dp, rhd::MODE_STAGE2, mixed, h->yhalf, state, state, h->rho, h->kP,
+                            h->kF, dt, h->err, h->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * n + 2], h->stream);
+  }
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(h, e, "timed step launch");
+  }
+  rhd_status st = finish(h);
+  stage_ms[0] = stage_ms[1] = 0.0;
+  for (int n = 0; n < nsteps; ++n) {
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, ev[2 * n], ev[2 * n + 1]) == hipSuccess) stage_ms[0] += a;
+    if (hipEventElapsedTime(&b, ev[2 * n + 1], ev[2 * n + 2]) == hipSuccess) stage_ms[1] += b;
+  }
+  cleanup();
+  return st;
+}
+
+rhd_status rhd_stage1(rhd_handle* h, const double* y, double* yh, double dt) {
+  if (!h) return RHD_EINVAL;
+  if (!y || !yh || y == yh || misaligned(y) || misaligned(yh) || !std::isfinite(dt) || !(dt > 0.0))
+    return set_err(h, RHD_EINVAL, -1, "invalid arguments");
+  hipError_t e = rhd::launch_reset_err(h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset");
+  e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, h->p.precision == RHD_MIXED, y, y, yh, h->rho,
+                        h->kP, h->kF, dt, h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stage 1 launch");
+  return finish(h);
+}
+
+rhd_status rhd_transport(rhd_handle* h, const double* y, double* s) {
+  if (!h) return RHD_EINVAL;
+  if (!y || !s || y == s || misaligned(y) || misaligned(s))
+    return set_err(h, RHD_EINVAL, -1, "invalid arguments");
+  hipError_t e = rhd::launch_reset_err(h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset");
+  e = rhd::launch_stage(h->dp, rhd::MODE_TRANSPORT, h->p.precision == RHD_MIXED, y, y, s, h->rho,
+                        h->kP, h->kF, 0.0, h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "transport launch");
+  return finish(h);
+}
+
+rhd_status rhd_source(rhd_handle* h, double* y, double tau) {
+  if (!h) return RHD_EINVAL;
+  if (!y || misaligned(y) || !std::isfinite(tau) || !(tau > 0.0))
+    return set_err(h, RHD_EINVAL, -1, "invalid arguments");
+  hipError_t e = rhd::launch_reset_err(h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset");
+  e = rhd::launch_source(h->dp, y, h->rho, h->kP, h->kF, tau, h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "source launch");
+  return finish(h);
+}
+
+rhd_status rhd_conserved_totals(rhd_handle* h, const double* state, double* out) {
+  if (!h) return RHD_EINVAL;
+  if (!state || !out || misaligned(state)) return set_err(h, RHD_EINVAL, -1, "invalid arguments");
+  const int no = 1 + h->p.ndim;
+  hipError_t e = rhd::launch_totals(h->dp, state, h->partial, h->partial_blocks, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "totals launch");
+  std::vector<double> part((size_t)h->partial_blocks * no);
+  e = hipMemcpyAsync(part.data(), h->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                     h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync(totals)");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  for (int m = 0; m < no; ++m) out[m] = 0.0;
+  for (int b = 0; b < h->partial_blocks; ++b)
+    for (int m = 0; m < no; ++m) out[m] += part[(size_t)b * no + m];
+  return set_err(h, RHD_OK, -1, "");
+}
+
+rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int32_t nsteps,
+                            double* lambda, double* g_kappa_P, double* g_kappa_F) {
+  if (!h) return RHD_EINVAL;
+  (void)state0; (void)dt; (void)nsteps; (void)lambda; (void)g_kappa_P; (void)g_kappa_F;
+  return set_err(h, RHD_EINVAL, -1, "adjoint not available in this build");
+}
+
+rhd_status rhd_last_error(const rhd_handle* h, int64_t* cell, char* msg, size_t len) {
+  if (!h) return RHD_EINVAL;
+  if (cell) *cell = h->last_cell;
+  if (msg && len > 0) {
+    std::snprintf(msg, len, "%s", h->last_msg.c_str());
+  }
+  return h->last;
+}
+
+void rhd_destroy(rhd_handle* h) { delete h; }
+
+}  // extern "C"

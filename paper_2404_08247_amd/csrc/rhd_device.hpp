@@ -1,0 +1,302 @@
+// Device math of the radiation step: PPM edge states, closure, HLL flux and the
+// local implicit source update. Everything here is a __device__ function; the
+// kernels that use it live in rhd_forward.hip and rhd_adjoint.hip.
+//
+// T is the arithmetic type of the transport stencil (double, or float in the
+// mixed-precision path); the source update is always double.
+#pragma once
+
+#include "rhd_internal.hpp"
+
+namespace rhd {
+
+// ---------------------------------------------------------------------------
+// PPM (Colella & Woodward 1984), method-of-lines form: limited slopes,
+// fourth-order interface values, monotonicity constraint on each cell's
+// parabola. The paper reconstructs E and F with PPM (Sec. 3.3).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T mc_slope(T am, T a0, T ap) {
+  const T dl = a0 - am;
+  const T dr = ap - a0;
+  const T dc = T(0.5) * (ap - am);
+  const T lim = fmin(fabs(dc), T(2) * fmin(fabs(dl), fabs(dr)));
+  return (dl * dr > T(0)) ? copysign(lim, dc) : T(0);
+}
+
+// interface value between cells with averages a0 | a1 and limited slopes d0 | d1
+template <typename T>
+__device__ __forceinline__ T ppm_iface(T a0, T a1, T d0, T d1) {
+  return T(0.5) * (a0 + a1) - (d1 - d0) * T(1.0 / 6.0);
+}
+
+// monotonised edge states (l, r) of a cell with average a from its raw
+// interface values
+template <typename T>
+__device__ __forceinline__ void ppm_monotone(T a, T& l, T& r) {
+  if ((r - a) * (a - l) <= T(0)) {
+    l = a;
+    r = a;
+  } else {
+    const T del = r - l;
+    const T a6 = T(6) * a - T(3) * (l + r);
+    const T del2 = del * del;
+    if (del * a6 > del2) {
+      l = T(3) * a - T(2) * r;
+    } else if (del * a6 < -del2) {
+      r = T(3) * a - T(2) * l;
+    }
+  }
+}
+
+// edge states of the middle cell of a[0..4]
+template <typename T>
+__device__ __forceinline__ void ppm_edges5(T a0, T a1, T a2, T a3, T a4, T& l, T& r) {
+  const T d1 = mc_slope(a0, a1, a2);
+  const T d2 = mc_slope(a1, a2, a3);
+  const T d3 = mc_slope(a2, a3, a4);
+  l = ppm_iface(a1, a2, d1, d2);
+  r = ppm_iface(a2, a3, d2, d3);
+  ppm_monotone(a2, l, r);
+}
+
+// ---------------------------------------------------------------------------
+// Closure: row D of P = D E along axis DIR. D = (1-chi)/2 I + (3chi-1)/2 n n,
+// chi = Levermore M1 Eddington factor of f = |F|/(cE) (clipped to 1), or 1/3.
+// ---------------------------------------------------------------------------
+template <int ND, int DIR, typename T>
+__device__ __forceinline__ void closure_row(int closure, T c, T E, const T* F, T* Drow) {
+  T F2 = T(0);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) F2 += F[k] * F[k];
+  T chi;
+  if (closure == 1) {
+    chi = T(1.0 / 3.0);
+  } else {
+    const T cE = c * E;
+    const T f2 = fmin(F2 / (cE * cE), T(1));
+    chi = (T(3) + T(4) * f2) / (T(5) + T(2) * sqrt(T(4) - T(3) * f2));
+  }
+  const T a = T(0.5) * (T(1) - chi);
+  const T b = T(0.5) * (T(3) * chi - T(1));
+  const T bn = (F2 > T(0)) ? (b / F2) * F[DIR] : T(0);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) Drow[k] = bn * F[k] + ((k == DIR) ? a : T(0));
+}
+
+// HLL flux along DIR between edge states Um = (E, F..) and Up (RSLA form):
+// Phi_E = (chat/c) F_DIR, Phi_Fk = c chat E D_DIR,k, speed chat sqrt(max D_DIR,DIR).
+template <int ND, int DIR, typename T>
+__device__ __forceinline__ void hll_flux(int closure, T c, T chat, T chat_over_c, T c_chat,
+                                         const T* Um, const T* Up, T* fl) {
+  T Dm[ND], Dp[ND];
+  closure_row<ND, DIR, T>(closure, c, Um[0], Um + 1, Dm);
+  closure_row<ND, DIR, T>(closure, c, Up[0], Up + 1, Dp);
+  const T hS = T(0.5) * chat * sqrt(fmax(Dm[DIR], Dp[DIR]));
+  fl[0] = T(0.5) * chat_over_c * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
+  const T em = c_chat * Um[0];
+  const T ep = c_chat * Up[0];
+#pragma unroll
+  for (int k = 0; k < ND; ++k)
+    fl[1 + k] = T(0.5) * (em * Dm[k] + ep * Dp[k]) - hS * (Up[1 + k] - Um[1 + k]);
+}
+
+// ---------------------------------------------------------------------------
+// Local implicit source update of one cell (Sec. 3.3), float64, in registers.
+// In: the state after the explicit part, y(t); out: y(t+1). tau = theta dt.
+// Returns 0, or ERR_NEWTON / ERR_NONPHYS bits.
+//
+// Inner stage: Newton-Raphson on x = (E_gas, R) for
+//   F_G = E_gas - E_gas(t) + (c/chat) R,   F_R = E(E_gas, R) - E(t) - R,
+// where R = -chat G0 tau (eq. Rnew) is solved for E with v, F and the closure
+// tensor D frozen: E = (A(T) + C - R/(tau chat)) / B. Jacobian as printed in
+// the paper (beta^2 terms dropped, d(kappa_P/kappa_E)/dT = 0). Stop when
+// |F_G| and (c/chat)|F_R| are below newton_rtol (E_gas(t) + (c/chat) E(t)).
+// Then E from energy conservation, F from eq. numF1/numF2, rho v from momentum
+// conservation; repeat with the new v and F until the v- and F-dependent part
+// of R changes by <= outer_rtol (relatively, or relative to R).
+// ---------------------------------------------------------------------------
+template <int ND>
+__device__ __forceinline__ void closure_full(int closure, double c, double E, const double* F,
+                                             double (*D)[ND]) {
+  double F2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) F2 += F[k] * F[k];
+  double chi;
+  if (closure == 1) {
+    chi = 1.0 / 3.0;
+  } else {
+    const double cE = c * E;
+    const double f2 = fmin(F2 / (cE * cE), 1.0);
+    chi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f2));
+  }
+  const double a = 0.5 * (1.0 - chi);
+  const double b = 0.5 * (3.0 * chi - 1.0);
+  const double bi = (F2 > 0.0) ? b / F2 : 0.0;
+#pragma unroll
+  for (int j = 0; j < ND; ++j)
+#pragma unroll
+    for (int k = 0; k < ND; ++k) D[j][k] = bi * F[j] * F[k] + ((j == k) ? a : 0.0);
+}
+
+template <int ND>
+__device__ unsigned source_cell(const DevParams& P, double& E, double* F, double& Eg, double* Pm,
+                                double rho, double kP, double kF, double tau) {
+  const double chiP = rho * kP;
+  const double chiE = chiP;
+  const double chiF = rho * kF;
+  if (chiP == 0.0 && chiF == 0.0) return 0u;
+  const double c = P.c, ch = P.chat;
+  const double k_cc = P.c_over_chat;
+  const double Cv = rho * P.cv_mass;
+  const double inv_Cv = 1.0 / Cv;
+  const double inv_rho = 1.0 / rho;
+  const double inv_tch = 1.0 / (tau * ch);
+  const double ar = P.a_r;
+
+  const double E0 = E, Eg0 = Eg;
+  double F0[ND], P0[ND], v[ND], Fb[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    F0[k] = F[k];
+    P0[k] = Pm[k];
+    v[k] = P0[k] * inv_rho;
+    Fb[k] = F0[k];
+  }
+  double Eb = E0;
+  double Egas = Eg0;
+  double R = 0.0;
+  const double tol = P.newton_rtol * (Eg0 + k_cc * E0);
+  // dF_R/dR of the simplified Jacobian; fixed for the call
+  const double J22 = -1.0 / (ch * chiE * tau) - 1.0;
+  const double J21c = 4.0 * chiP * ar / (chiE * Cv);
+  const double ctau = ch * tau;
+
+  double Enew = E0, Fnew[ND], Pnew[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    Fnew[k] = F0[k];
+    Pnew[k] = P0[k];
+  }
+  unsigned status = 0u;
+
+  for (int ko = 0; ko < P.outer_maxit; ++ko) {
+    double v2 = 0.0, vF = 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      v2 += v[k] * v[k];
+      vF += v[k] * Fb[k];
+    }
+    const double KE = 0.5 * rho * v2;
+    const double b2 = v2 * P.inv_c2;
+    double D[ND][ND];
+    closure_full<ND>(P.closure, c, Eb, Fb, D);
+    double Dv[ND];
+    double vDv = 0.0;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) s += D[j][k] * v[k];
+      Dv[j] = s;
+      vDv += v[j] * s;
+    }
+    const bool o2 = (P.v_order == 2);
+    const double Afac = o2 ? 1.0 + 0.5 * b2 : 1.0;
+    const double B = o2 ? chiE * (1.0 + 0.5 * b2) - (chiF - chiE) * (b2 + vDv * P.inv_c2) : chiE;
+    const double inv_B = 1.0 / B;
+    const double Cc = (2.0 * chiE - chiF) * vF * P.inv_c2;
+    const double Aco = chiP * ar * Afac;
+
+    // ---- inner Newton on (E_gas, R) ----
+    bool conv = false;
+    for (int it = 0;; ++it) {
+      const double T = (Egas - KE) * inv_Cv;
+      const double T2 = T * T;
+      const double Er = (Aco * T2 * T2 + Cc - R * inv_tch) * inv_B;
+      const double FG = Egas - Eg0 + k_cc * R;
+      const double FR = Er - E0 - R;
+      if (fabs(FG) < tol && k_cc * fabs(FR) < tol) {
+        conv = true;
+        break;
+      }
+      if (it >= P.newton_maxit) break;
+      const double J21 = J21c * T2 * T;
+      const double inv_det = 1.0 / (J22 - k_cc * J21);
+      Egas += (k_cc * FR - J22 * FG) * inv_det;
+      R += (J21 * FG - FR) * inv_det;
+    }
+    if (!conv) {
+      status |= ERR_NEWTON;
+      break;
+    }
+
+    // ---- energy from conservation; flux and momentum ----
+    Enew = E0 - P.chat_over_c * (Egas - Eg0);
+    const double Tn = (Egas - KE) * inv_Cv;
+    const double Tn2 = Tn * Tn;
+    const double Bn = ar * Tn2 * Tn2;
+    const double inv_den = o2 ? 1.0 / (1.0 + ctau * chiF * (1.0 + 0.5 * b2)) : 1.0 / (1.0 + ctau * chiF);
+    const double xv = chiP * Bn + (o2 ? 0.0 : (chiF - chiE) * Enew);
+    double vnew[ND];
+    double v2n = 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      Fnew[k] = (F0[k] + ctau * (xv * v[k] + chiF * Enew * Dv[k])) * inv_den;
+      Pnew[k] = P0[k] - (Fnew[k] - F0[k]) * P.inv_c_chat;
+      vnew[k] = Pnew[k] * inv_rho;
+      v2n += vnew[k] * vnew[k];
+    }
+
+    // ---- outer test on the v- and F-dependent part of R ----
+    double wF_old = 0.0, wF_new = 0.0, wDw_new = 0.0;
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      wF_old += v[j] * Fb[j];
+      wF_new += vnew[j] * Fnew[j];
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) s += D[j][k] * vnew[k];
+      wDw_new += vnew[j] * s;
+    }
+    double W_old = (2.0 * chiE - chiF) * wF_old * P.inv_c2;
+    double W_new = (2.0 * chiE - chiF) * wF_new * P.inv_c2;
+    if (o2) {
+      const double b2n = v2n * P.inv_c2;
+      const double Tq = (Egas - 0.5 * rho * v2n) * inv_Cv;
+      const double Tq2 = Tq * Tq;
+      W_old += (chiP * Bn - chiE * Enew) * 0.5 * b2 + (chiF - chiE) * (b2 * Enew + Enew * vDv * P.inv_c2);
+      W_new += (chiP * ar * Tq2 * Tq2 - chiE * Enew) * 0.5 * b2n +
+               (chiF - chiE) * (b2n * Enew + Enew * wDw_new * P.inv_c2);
+    }
+    W_old *= ctau;
+    W_new *= ctau;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      v[k] = vnew[k];
+      Fb[k] = Fnew[k];
+    }
+    Eb = Enew;
+    R = Enew - E0;
+    const double dW = fabs(W_new - W_old);
+    if (dW <= P.outer_rtol * fabs(W_old) || dW <= P.outer_rtol * fabs(R)) break;
+  }
+
+  if (status == 0u) {
+    double p2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) p2 += Pnew[k] * Pnew[k];
+    const double eint = Egas - 0.5 * p2 * inv_rho;
+    if (!(eint > 0.0) || !(Enew > 0.0)) status |= ERR_NONPHYS;
+  }
+  E = Enew;
+  Eg = Egas;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    F[k] = Fnew[k];
+    Pm[k] = Pnew[k];
+  }
+  return status;
+}
+
+}  // namespace rhd

@@ -1,0 +1,485 @@
+// Forward kernels of the radiation step for gfx950.
+//
+// One fused kernel per PD-ARS stage (Sec. 3.2, eq. imex1 / imex2): the explicit
+// transport s(y) of (E, F) and the local implicit source of every cell of a tile
+// run in the same launch, so y(t) never goes to HBM.
+//
+// Tiling. A workgroup of 256 threads owns a TX x TY column of cells (32 x 8 in
+// 2-D/3-D, 256 x 1 in 1-D) and marches along z over a chunk of planes:
+//  - x and y faces: the plane's (E, F) tile with a 3-cell halo is staged in LDS;
+//    PPM edge states are computed once per cell and HLL fluxes once per face,
+//    both as flattened loops over the tile so the halo work is spread over the
+//    whole workgroup; fluxes are written back into the tile's LDS.
+//  - z faces: each thread keeps its own column's PPM pipeline in registers
+//    (values k+1..k+3, the limited slope and raw interface value ahead, the
+//    monotonised right edge of cell k and the z-flux below), so every z-face is
+//    computed once and z needs neither LDS nor a halo exchange.
+// Halo cells come from the ghost rule (periodic wrap, or mirror with the normal
+// flux component negated), applied on load.
+#include <climits>
+
+#include "rhd_device.hpp"
+
+namespace rhd {
+
+constexpr int HALO = 3;
+constexpr int NTHREADS = 256;
+
+template <int ND> struct TileShape;
+template <> struct TileShape<1> { static constexpr int TX = 256, TY = 1; };
+template <> struct TileShape<2> { static constexpr int TX = 32, TY = 8; };
+template <> struct TileShape<3> { static constexpr int TX = 32, TY = 8; };
+
+// Ghost rule along one axis: returns the source cell of (possibly outside)
+// coordinate g and whether the normal flux component flips sign. Positions
+// further than HALO outside the grid are clamped; no real cell's stencil
+// reads them.
+__device__ __forceinline__ int ghost(int g, int n, int bc, bool& flip) {
+  flip = false;
+  if (g >= 0 && g < n) return g;
+  if (bc == 0) {
+    int m = g % n;
+    return m < 0 ? m + n : m;
+  }
+  flip = true;
+  int m = (g < 0) ? -1 - g : 2 * n - 1 - g;
+  return m < 0 ? 0 : (m >= n ? n - 1 : m);
+}
+
+__device__ __forceinline__ long long cidx(const DevParams& P, int x, int y, int z) {
+  return ((long long)z * P.n[1] + y) * P.n[0] + x;
+}
+
+__device__ __forceinline__ void report(unsigned long long* err, long long cell, unsigned bits) {
+  atomicMin(err, (unsigned long long)cell);
+  atomicOr(reinterpret_cast<unsigned int*>(err + 1), bits);
+}
+
+template <int ND, int MODE, typename TT>
+__global__ void __launch_bounds__(NTHREADS)
+k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw,
+        const double* __restrict__ rho, const double* __restrict__ kP,
+        const double* __restrict__ kF, double dt, int zchunk, unsigned long long* err) {
+  constexpr int TX = TileShape<ND>::TX;
+  constexpr int TY = TileShape<ND>::TY;
+  constexpr int NR = 1 + ND;                 // radiation variables E, F_1..F_ND
+  constexpr int TW = TX + 2 * HALO;          // tile row length
+  constexpr int TH = (ND >= 2) ? TY + 2 * HALO : 1;
+  constexpr int NTILE = TW * TH;
+  constexpr int NEX = (TX + 2) * TY;         // cells that need x edge states
+  constexpr int NEY = (ND >= 2) ? TX * (TY + 2) : 0;
+  constexpr int NFX = (TX + 1) * TY;         // x faces
+  constexpr int NFY = (ND >= 2) ? TX * (TY + 1) : 0;
+  constexpr int AREA = (NTILE > NFX + NFY) ? NTILE : NFX + NFY;
+  constexpr int NEYs = NEY > 0 ? NEY : 1;
+
+  __shared__ TT s_area[NR][AREA];            // (E, F) tile, then face fluxes
+  __shared__ TT s_exL[NR][NEX], s_exR[NR][NEX];
+  __shared__ TT s_eyL[NR][NEYs], s_eyR[NR][NEYs];
+
+  const int tid = threadIdx.x;
+  const int tx = tid % TX;
+  const int ty = tid / TX;
+  const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  const int x0 = blockIdx.x * TX;
+  const int y0 = blockIdx.y * TY;
+  const int z0 = blockIdx.z * zchunk;
+  const int z1 = min(z0 + zchunk, nz);
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool valid = (gx < nx) && (gy < ny);
+  bool fl_;
+  const int cx = ghost(gx, nx, P.bc[0], fl_);   // in-range column for loads
+  const int cy = (ND >= 2) ? ghost(gy, ny, P.bc[1], fl_) : 0;
+  const long long N = P.N;
+
+  const TT c = TT(P.c), ch = TT(P.chat), chc = TT(P.chat_over_c), cch = TT(P.c_chat);
+  const int clo = P.closure;
+
+  // ---- z pipeline state (ND == 3) ----
+  TT zv1[NR], zv2[NR], zdm[NR], zI[NR], zaR[NR], zc[NR];
+  TT zfl_prev[NR];
+  if constexpr (ND == 3) {
+    TT w[6][NR];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      bool flip;
+      const int gz = ghost(z0 - 3 + m, nz, P.bc[2], flip);
+      const long long q = cidx(P, cx, cy, gz);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        TT val = TT(ys[r * N + q]);
+        w[m][r] = (flip && r == 3) ? -val : val;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const TT dA = mc_slope(w[0][r], w[1][r], w[2][r]);   // z0-2
+      const TT dB = mc_slope(w[1][r], w[2][r], w[3][r]);   // z0-1
+      const TT dC = mc_slope(w[2][r], w[3][r], w[4][r]);   // z0
+      const TT dD = mc_slope(w[3][r], w[4][r], w[5][r]);   // z0+1
+      TT Im = ppm_iface(w[1][r], w[2][r], dA, dB);         // z0-3/2
+      TT I0 = ppm_iface(w[2][r], w[3][r], dB, dC);         // z0-1/2
+      TT Ip = ppm_iface(w[3][r], w[4][r], dC, dD);         // z0+1/2
+      TT lm = Im, rm = I0;
+      ppm_monotone(w[2][r], lm, rm);                       // cell z0-1
+      TT l0 = I0, r0 = Ip;
+      ppm_monotone(w[3][r], l0, r0);                       // cell z0
+      zaR[r] = r0;
+      zI[r] = Ip;
+      zdm[r] = dD;
+      zc[r] = w[3][r];
+      zv1[r] = w[4][r];
+      zv2[r] = w[5][r];
+      w[0][r] = rm;   // reuse as the z0-1/2 face states
+      w[1][r] = l0;
+    }
+    TT Um[NR], Up[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      Um[r] = w[0][r];
+      Up[r] = w[1][r];
+    }
+    hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, Um, Up, zfl_prev);
+  }
+
+  for (int k = z0; k < z1; ++k) {
+    // ---------------- stage the plane's (E, F) tile in LDS ----------------
+    TT own[NR];
+    if constexpr (ND == 3) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) own[r] = zc[r];
+    } else {
+      const long long q = cidx(P, cx, cy, k);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) own[r] = TT(ys[r * N + q]);
+    }
+    {
+      const int t = (ty + (ND >= 2 ? HALO : 0)) * TW + tx + HALO;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) s_area[r][t] = own[r];
+    }
+    // halo: 3 columns left and right of every row; 3 rows above and below
+    constexpr int NHX = 2 * HALO * TY;
+    constexpr int NHY = (ND >= 2) ? 2 * HALO * TX : 0;
+    for (int h = tid; h < NHX + NHY; h += NTHREADS) {
+      int lx, ly;
+      if (h < NHX) {
+        const int row = h / (2 * HALO), j = h % (2 * HALO);
+        lx = (j < HALO) ? j : TX + j;       // tile column
+        ly = row + (ND >= 2 ? HALO : 0);
+      } else {
+        const int h2 = h - NHX;
+        const int col = h2 % TX, j = h2 / TX;
+        lx = col + HALO;
+        ly = (j < HALO) ? j : TY + j;
+      }
+      bool fx, fy = false;
+      const int sx = ghost(x0 + lx - HALO, nx, P.bc[0], fx);
+      const int sy = (ND >= 2) ? ghost(y0 + ly - HALO, ny, P.bc[1], fy) : 0;
+      const long long q = cidx(P, sx, sy, k);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        TT val = TT(ys[r * N + q]);
+        if ((fx && r == 1) || (fy && r == 2)) val = -val;
+        s_area[r][ly * TW + lx] = val;
+      }
+    }
+    __syncthreads();
+
+    // ---------------- PPM edge states, once per cell ----------------
+    for (int e = tid; e < NEX + NEY; e += NTHREADS) {
+      if (e < NEX) {
+        const int row = e / (TX + 2), col = e % (TX + 2);    // cell x0 + col - 1
+        const int base = (row + (ND >= 2 ? HALO : 0)) * TW + col;  // = centre - 2
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const TT* a = &s_area[r][base];
+          TT l, rr;
+          ppm_edges5(a[0], a[1], a[2], a[3], a[4], l, rr);
+          s_exL[r][e] = l;
+          s_exR[r][e] = rr;
+        }
+      } else if constexpr (ND >= 2) {
+        const int e2 = e - NEX;
+        const int col = e2 % TX, row = e2 / TX;              // cell y0 + row - 1
+        const int base = row * TW + col + HALO;              // = centre - 2 rows
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const TT* a = &s_area[r][base];
+          TT l, rr;
+          ppm_edges5(a[0], a[TW], a[2 * TW], a[3 * TW], a[4 * TW], l, rr);
+          s_eyL[r][e2] = l;
+          s_eyR[r][e2] = rr;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---------------- HLL fluxes, once per face (into the tile's LDS) -------
+    for (int f = tid; f < NFX + NFY; f += NTHREADS) {
+      TT Um[NR], Up[NR], fl[NR];
+      if (f < NFX) {
+        const int row = f / (TX + 1), fx = f % (TX + 1);     // between cells fx-1 | fx
+        const int eb = row * (TX + 2) + fx;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          Um[r] = s_exR[r][eb];
+          Up[r] = s_exL[r][eb + 1];
+        }
+        hll_flux<ND, 0, TT>(clo, c, ch, chc, cch, Um, Up, fl);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s_area[r][f] = fl[r];
+      } else if constexpr (ND >= 2) {
+        const int f2 = f - NFX;
+        const int col = f2 % TX, fy = f2 / TX;               // between rows fy-1 | fy
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          Um[r] = s_eyR[r][fy * TX + col];
+          Up[r] = s_eyL[r][(fy + 1) * TX + col];
+        }
+        hll_flux<ND, (ND >= 2 ? 1 : 0), TT>(clo, c, ch, chc, cch, Um, Up, fl);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s_area[r][NFX + f2] = fl[r];
+      }
+    }
+
+    // ---------------- z face k+1/2 from the register pipeline ----------------
+    double divz[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) divz[r] = 0.0;
+    if constexpr (ND == 3) {
+      bool flip;
+      const int gz = ghost(k + 3, nz, P.bc[2], flip);
+      const long long q = cidx(P, cx, cy, gz);
+      TT aL1[NR], aR1[NR], fz[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        TT w3 = TT(ys[r * N + q]);
+        if (flip && r == 3) w3 = -w3;
+        const TT d2 = mc_slope(zv1[r], zv2[r], w3);
+        const TT I2 = ppm_iface(zv1[r], zv2[r], zdm[r], d2);
+        TT l = zI[r], rr = I2;
+        ppm_monotone(zv1[r], l, rr);
+        aL1[r] = l;
+        aR1[r] = rr;
+        zI[r] = I2;
+        zdm[r] = d2;
+        zc[r] = zv1[r];
+        zv1[r] = zv2[r];
+        zv2[r] = w3;
+      }
+      hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, zaR, aL1, fz);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        divz[r] = double(fz[r]) - double(zfl_prev[r]);
+        zfl_prev[r] = fz[r];
+        zaR[r] = aR1[r];
+      }
+    }
+    __syncthreads();
+
+    // ---------------- divergence of the own cell ----------------
+    double s[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      double d = double(s_area[r][ty * (TX + 1) + tx + 1]) - double(s_area[r][ty * (TX + 1) + tx]);
+      if constexpr (ND >= 2)
+        d += double(s_area[r][NFX + (ty + 1) * TX + tx]) - double(s_area[r][NFX + ty * TX + tx]);
+      d += divz[r];
+      s[r] = -d * P.inv_dx;
+    }
+    if (k + 1 < z1) __syncthreads();   // LDS is restaged for the next plane
+
+    if (!valid) continue;
+    const long long q = cidx(P, gx, gy, k);
+    if constexpr (MODE == MODE_TRANSPORT) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) yw[r * N + q] = s[r];
+#pragma unroll
+      for (int r = NR; r < 2 + 2 * ND; ++r) yw[r * N + q] = 0.0;
+      continue;
+    } else {
+      // y(t): stage 1 = y^n + dt s(y^n); stage 2 = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2})
+      double E, F[ND], Eg, Pm[ND];
+      double tau;
+      if constexpr (MODE == MODE_STAGE1) {
+        E = ys[q] + dt * s[0];
+#pragma unroll
+        for (int k2 = 0; k2 < ND; ++k2) F[k2] = ys[(1 + k2) * N + q] + dt * s[1 + k2];
+        Eg = ys[(1 + ND) * N + q];
+#pragma unroll
+        for (int k2 = 0; k2 < ND; ++k2) Pm[k2] = ys[(2 + ND + k2) * N + q];
+        tau = dt;
+      } else {
+        const double hdt = 0.5 * dt;
+        E = 0.5 * (yo[q] + ys[q]) + hdt * s[0];
+#pragma unroll
+        for (int k2 = 0; k2 < ND; ++k2)
+          F[k2] = 0.5 * (yo[(1 + k2) * N + q] + ys[(1 + k2) * N + q]) + hdt * s[1 + k2];
+        Eg = 0.5 * (yo[(1 + ND) * N + q] + ys[(1 + ND) * N + q]);
+#pragma unroll
+        for (int k2 = 0; k2 < ND; ++k2)
+          Pm[k2] = 0.5 * (yo[(2 + ND + k2) * N + q] + ys[(2 + ND + k2) * N + q]);
+        tau = hdt;
+      }
+      const double kp = kP[q];
+      const double kf = P.kF_alias ? kp : kF[q];
+      const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, kf, tau);
+      if (st) report(err, q, st);
+      yw[q] = E;
+#pragma unroll
+      for (int k2 = 0; k2 < ND; ++k2) yw[(1 + k2) * N + q] = F[k2];
+      yw[(1 + ND) * N + q] = Eg;
+#pragma unroll
+      for (int k2 = 0; k2 < ND; ++k2) yw[(2 + ND + k2) * N + q] = Pm[k2];
+    }
+  }
+}
+
+// Source only (no transport), one cell per thread.
+template <int ND>
+__global__ void __launch_bounds__(NTHREADS)
+k_source(DevParams P, double* y, const double* __restrict__ rho, const double* __restrict__ kP,
+         const double* __restrict__ kF, double tau, unsigned long long* err) {
+  const long long q = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (q >= P.N) return;
+  const long long N = P.N;
+  double E = y[q], Eg = y[(1 + ND) * N + q], F[ND], Pm[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    F[k] = y[(1 + k) * N + q];
+    Pm[k] = y[(2 + ND + k) * N + q];
+  }
+  const double kp = kP[q];
+  const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q], tau);
+  if (st) report(err, q, st);
+  y[q] = E;
+  y[(1 + ND) * N + q] = Eg;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    y[(1 + k) * N + q] = F[k];
+    y[(2 + ND + k) * N + q] = Pm[k];
+  }
+}
+
+__global__ void k_reset_err(unsigned long long* err) {
+  if (threadIdx.x == 0) {
+    err[0] = ULLONG_MAX;
+    err[1] = 0ull;
+  }
+}
+
+// Per-block partial sums of the conserved totals (diagnostics).
+template <int ND>
+__global__ void __launch_bounds__(NTHREADS)
+k_totals(DevParams P, const double* __restrict__ y, double* __restrict__ partial) {
+  constexpr int NO = 1 + ND;
+  __shared__ double red[NO][NTHREADS];
+  double acc[NO];
+#pragma unroll
+  for (int m = 0; m < NO; ++m) acc[m] = 0.0;
+  const long long N = P.N;
+  for (long long q = (long long)blockIdx.x * NTHREADS + threadIdx.x; q < N;
+       q += (long long)gridDim.x * NTHREADS) {
+    acc[0] += y[(1 + ND) * N + q] + P.c_over_chat * y[q];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) acc[1 + k] += y[(2 + ND + k) * N + q] + y[(1 + k) * N + q] * P.inv_c_chat;
+  }
+#pragma unroll
+  for (int m = 0; m < NO; ++m) red[m][threadIdx.x] = acc[m];
+  __syncthreads();
+  for (int s = NTHREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int m = 0; m < NO; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < NO; ++m) partial[blockIdx.x * NO + m] = red[m][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int ND, int MODE, typename TT>
+static hipError_t launch_nd(const DevParams& P, const double* ys, const double* yo, double* yw,
+                            const double* rho, const double* kP, const double* kF, double dt,
+                            unsigned long long* err, hipStream_t s) {
+  constexpr int TX = TileShape<ND>::TX, TY = TileShape<ND>::TY;
+  const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  const int gxn = (nx + TX - 1) / TX, gyn = (ny + TY - 1) / TY;
+  int zchunk = nz;
+  if (ND == 3) {
+    // enough workgroups to fill 256 CUs several times, chunks of >= 8 planes
+    const long long cols = (long long)gxn * gyn;
+    zchunk = 16;
+    while (zchunk > 8 && cols * ((nz + zchunk - 1) / zchunk) < 2048) zchunk /= 2;
+    if (zchunk > nz) zchunk = nz;
+  }
+  const int gzn = (nz + zchunk - 1) / zchunk;
+  hipLaunchKernelGGL((k_stage<ND, MODE, TT>), dim3(gxn, gyn, gzn), dim3(NTHREADS), 0, s, P, ys,
+                     yo, yw, rho, kP, kF, dt, zchunk, err);
+  return hipGetLastError();
+}
+
+template <int MODE, typename TT>
+static hipError_t launch_mode(const DevParams& P, const double* ys, const double* yo, double* yw,
+                              const double* rho, const double* kP, const double* kF, double dt,
+                              unsigned long long* err, hipStream_t s) {
+  switch (P.ndim) {
+    case 1: return launch_nd<1, MODE, TT>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 2: return launch_nd<2, MODE, TT>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 3: return launch_nd<3, MODE, TT>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* ysten,
+                        const double* yown, double* yout, const double* rho, const double* kP,
+                        const double* kF, double dt, unsigned long long* err, hipStream_t s) {
+  if (mixed) {
+    switch (mode) {
+      case MODE_STAGE1: return launch_mode<MODE_STAGE1, float>(P, ysten, yown, yout, rho, kP, kF, dt, err, s);
+      case MODE_STAGE2: return launch_mode<MODE_STAGE2, float>(P, ysten, yown, yout, rho, kP, kF, dt, err, s);
+      default: return launch_mode<MODE_TRANSPORT, float>(P, ysten, yown, yout, rho, kP, kF, dt, err, s);
+    }
+  }
+  switch (mode) {
+    case MODE_STAGE1: return launch_mode<MODE_STAGE1, double>(P, ysten, yown, yout, rho, kP, kF, dt, err, s);
+    case MODE_STAGE2: return launch_mode<MODE_STAGE2, double>(P, ysten, yown, yout, rho, kP, kF, dt, err, s);
+    default: return launch_mode<MODE_TRANSPORT, double>(P, ysten, yown, yout, rho, kP, kF, dt, err, s);
+  }
+}
+
+hipError_t launch_source(const DevParams& P, double* y, const double* rho, const double* kP,
+                         const double* kF, double tau, unsigned long long* err, hipStream_t s) {
+  const unsigned blocks = (unsigned)((P.N + NTHREADS - 1) / NTHREADS);
+  switch (P.ndim) {
+    case 1: hipLaunchKernelGGL(k_source<1>, dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 2: hipLaunchKernelGGL(k_source<2>, dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 3: hipLaunchKernelGGL(k_source<3>, dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_err(unsigned long long* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_err, dim3(1), dim3(64), 0, s, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const DevParams& P, const double* y, double* partial, int nblocks,
+                         hipStream_t s) {
+  switch (P.ndim) {
+    case 1: hipLaunchKernelGGL(k_totals<1>, dim3(nblocks), dim3(NTHREADS), 0, s, P, y, partial); break;
+    case 2: hipLaunchKernelGGL(k_totals<2>, dim3(nblocks), dim3(NTHREADS), 0, s, P, y, partial); break;
+    case 3: hipLaunchKernelGGL(k_totals<3>, dim3(nblocks), dim3(NTHREADS), 0, s, P, y, partial); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rhd

@@ -1,0 +1,46 @@
+// Internal declarations shared by the host runtime (rhd_api.cpp) and the HIP
+// kernels (rhd_forward.hip, rhd_adjoint.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace rhd {
+
+// Kernel-side constants of one handle, passed by value to every launch.
+struct DevParams {
+  int ndim;
+  int closure;        // 0 = M1, 1 = Eddington
+  int v_order;        // 1 or 2
+  int bc[3];          // 0 periodic, 1 reflect
+  int n[3];           // nx, ny, nz
+  int newton_maxit;
+  int outer_maxit;
+  long long N;        // cells
+  double dx, inv_dx;
+  double c, chat;
+  double c_over_chat, chat_over_c, c_chat, inv_c_chat, inv_c2;
+  double a_r;
+  double cv_mass;     // kB_over_mu / (gamma - 1)
+  double newton_rtol, outer_rtol;
+  int kF_alias;       // 1: kappa_F == kappa_P
+};
+
+// Device error word layout (in the workspace): [0] smallest failing cell
+// (initialised to INT64_MAX), [1] bit mask of failure kinds.
+enum : unsigned { ERR_NEWTON = 1u, ERR_NONPHYS = 2u };
+
+enum StageMode : int { MODE_STAGE1 = 0, MODE_STAGE2 = 1, MODE_TRANSPORT = 2 };
+
+// Forward launchers (rhd_forward.hip). All return hipSuccess or the launch error.
+hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* ysten,
+                        const double* yown, double* yout, const double* rho, const double* kP,
+                        const double* kF, double dt, unsigned long long* err, hipStream_t s);
+hipError_t launch_source(const DevParams& P, double* y, const double* rho, const double* kP,
+                         const double* kF, double tau, unsigned long long* err, hipStream_t s);
+hipError_t launch_reset_err(unsigned long long* err, hipStream_t s);
+hipError_t launch_totals(const DevParams& P, const double* y, double* partial, int nblocks,
+                         hipStream_t s);
+
+}  // namespace rhd

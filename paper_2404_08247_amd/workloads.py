@@ -144,12 +144,12 @@ def _radial_r2_cells(n, ndim):
     return r2
 
 
-def config1(n: int = 256, nsteps: int = 1000, **over) -> Workload:
+def config1(n: int = 256, nsteps: int = 1000, bc=(1,), **over) -> Workload:
     """1-D, reflecting walls, FP64: optically thick (tau_cell = 10) Gaussian
     radiation pulse T = 1 + 10 exp(-(x - 1/2)^2 / 0.05^2), gas in equilibrium,
     F = 0, v = 0, chat = c."""
     chat = 1.0
-    p = base_params(1, (n,), chat, (1,), **over)
+    p = base_params(1, (n,), chat, bc, **over)
     dx = p["dx"]
     x = cell_centres(n)
     T = 1.0 + 10.0 * np.exp(-((x - 0.5) ** 2) / 0.05 ** 2)
@@ -163,13 +163,13 @@ def config1(n: int = 256, nsteps: int = 1000, **over) -> Workload:
 
 
 def config2(n: Sequence[int] = (128, 128, 128), nsteps: int = 200, precision="fp64",
-            **over) -> Workload:
+            bc=(0, 0, 0), **over) -> Workload:
     """3-D static mixed-regime grid, periodic: log10 tau_cell = clip(N(0,1), -3, 3)
     i.i.d.; T = 1 + 0.1 GRF(8 cells); T_rad = T (1 + U(-0.2, 0.2)) i.i.d.;
     E = a_r T_rad^4; F = 0; v = 0; chat = c/100."""
     rng = np.random.default_rng(SEED_BASE + 2)
     chat = 0.01
-    p = base_params(3, n, chat, (0, 0, 0), precision=precision, **over)
+    p = base_params(3, n, chat, bc, precision=precision, **over)
     nx, ny, nz = p["n"]
     dx = p["dx"]
     shape = (nz, ny, nx)
@@ -185,14 +185,14 @@ def config2(n: Sequence[int] = (128, 128, 128), nsteps: int = 200, precision="fp
 
 
 def config3(n: Sequence[int] = (256, 256, 256), nsteps: int = 300, precision="mixed",
-            sigma_cells: Optional[float] = None, **over) -> Workload:
+            sigma_cells: Optional[float] = None, bc=(0, 0, 0), **over) -> Workload:
     """3-D dynamic diffusion, periodic: uniform v = 0.01 c along x; 8 x-slabs, each
     slab's tau_cell drawn from {0.1, 10, 1000}; T = 1 + exp(-r^2 / (2 sigma^2)),
     sigma = 16 cells (scaled with nx/256 on smaller grids), centred; E = a_r T^4;
     F = (4/3) v E (comoving equilibrium to O(v/c)); chat = c/50."""
     rng = np.random.default_rng(SEED_BASE + 3)
     chat = 0.02
-    p = base_params(3, n, chat, (0, 0, 0), precision=precision, **over)
+    p = base_params(3, n, chat, bc, precision=precision, **over)
     nx, ny, nz = p["n"]
     dx = p["dx"]
     shape = (nz, ny, nx)
@@ -230,14 +230,14 @@ def central_patch(n: Sequence[int], ndim: int, width: int) -> np.ndarray:
 
 
 def config4(n: Sequence[int] = (512, 512), nsteps: int = 200, ckpt_every: int = 20,
-            **over) -> Workload:
+            bc=(0, 0), **over) -> Workload:
     """2-D adjoint run, FP64, periodic: log10 tau_cell = clip(N(0, 2/3), -2, 2)
     i.i.d.; v per component = GRF(8), scaled so max |v| = 0.005 c;
     T = 1 + exp(-r^2 / (2 (32 nx/512)^2)) centred; E = a_r T^4; F = 0; chat = c.
     Objective J = sum of E over the central (nx/8) x (ny/8) patch."""
     rng = np.random.default_rng(SEED_BASE + 4)
     chat = 1.0
-    p = base_params(2, n, chat, (0, 0), **over)
+    p = base_params(2, n, chat, bc, **over)
     nx, ny, nz = p["n"]
     dx = p["dx"]
     shape = (1, ny, nx)
@@ -258,14 +258,14 @@ def config4(n: Sequence[int] = (512, 512), nsteps: int = 200, ckpt_every: int = 
 
 
 def config5(n: Sequence[int] = (320, 320, 320), nsteps: int = 100, ckpt_every: int = 10,
-            precision="mixed", **over) -> Workload:
+            precision="mixed", bc=(0, 0, 0), **over) -> Workload:
     """3-D forward + adjoint, periodic: tau_cell as config 2; velocity random-phase
     field with |v_hat(k)| ~ |k|^-2, rms |v| = 0.01 c; T = exp(0.1 GRF(8));
     E = a_r T^4; F = 0; chat = c/100. J = sum of E over the central (n/5)^3 block
     (64^3 at 320^3)."""
     rng = np.random.default_rng(SEED_BASE + 5)
     chat = 0.01
-    p = base_params(3, n, chat, (0, 0, 0), precision=precision, **over)
+    p = base_params(3, n, chat, bc, precision=precision, **over)
     nx, ny, nz = p["n"]
     dx = p["dx"]
     shape = (nz, ny, nx)
