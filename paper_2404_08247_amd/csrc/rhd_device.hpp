@@ -11,94 +11,122 @@
 namespace rhd {
 
 // ---------------------------------------------------------------------------
+// Reciprocal: hardware estimate refined by two Newton-Raphson steps
+// (r <- r + r (1 - x r)), full double precision for the positive, normal
+// arguments it is used on.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ---------------------------------------------------------------------------
 // PPM (Colella & Woodward 1984), method-of-lines form: limited slopes,
 // fourth-order interface values, monotonicity constraint on each cell's
-// parabola. The paper reconstructs E and F with PPM (Sec. 3.3).
+// parabola (the paper reconstructs E and F with PPM, Sec. 3.3).
+//
+// Delta form: every quantity is an offset from the cell's own average, formed
+// in double and then handled in T, so the float path keeps the relative
+// precision of the (small) differences instead of that of the values.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T mc_slope(T am, T a0, T ap) {
-  const T dl = a0 - am;
-  const T dr = ap - a0;
-  const T dc = T(0.5) * (ap - am);
+__device__ __forceinline__ T mc_slope(T dl, T dr) {   // dl = a0 - a(-1), dr = a(+1) - a0
+  const T dc = T(0.5) * (dl + dr);
   const T lim = fmin(fabs(dc), T(2) * fmin(fabs(dl), fabs(dr)));
   return (dl * dr > T(0)) ? copysign(lim, dc) : T(0);
 }
 
-// interface value between cells with averages a0 | a1 and limited slopes d0 | d1
+// monotonised edge offsets (l, r) of a cell from its raw interface offsets
 template <typename T>
-__device__ __forceinline__ T ppm_iface(T a0, T a1, T d0, T d1) {
-  return T(0.5) * (a0 + a1) - (d1 - d0) * T(1.0 / 6.0);
-}
-
-// monotonised edge states (l, r) of a cell with average a from its raw
-// interface values
-template <typename T>
-__device__ __forceinline__ void ppm_monotone(T a, T& l, T& r) {
-  if ((r - a) * (a - l) <= T(0)) {
-    l = a;
-    r = a;
+__device__ __forceinline__ void ppm_monotone(T& l, T& r) {
+  if (r * l >= T(0)) {          // (r - 0)(0 - l) <= 0: local extremum
+    l = T(0);
+    r = T(0);
   } else {
     const T del = r - l;
-    const T a6 = T(6) * a - T(3) * (l + r);
+    const T a6 = T(-3) * (l + r);
     const T del2 = del * del;
     if (del * a6 > del2) {
-      l = T(3) * a - T(2) * r;
+      l = T(-2) * r;
     } else if (del * a6 < -del2) {
-      r = T(3) * a - T(2) * l;
+      r = T(-2) * l;
     }
   }
 }
 
-// edge states of the middle cell of a[0..4]
+// edge states of the middle cell of a[0..4] (double values in, double out)
 template <typename T>
-__device__ __forceinline__ void ppm_edges5(T a0, T a1, T a2, T a3, T a4, T& l, T& r) {
-  const T d1 = mc_slope(a0, a1, a2);
-  const T d2 = mc_slope(a1, a2, a3);
-  const T d3 = mc_slope(a2, a3, a4);
-  l = ppm_iface(a1, a2, d1, d2);
-  r = ppm_iface(a2, a3, d2, d3);
-  ppm_monotone(a2, l, r);
+__device__ __forceinline__ void ppm_edges5(double a0, double a1, double a2, double a3, double a4,
+                                           double& l, double& r) {
+  const T d01 = T(a1 - a0), d12 = T(a2 - a1), d23 = T(a3 - a2), d34 = T(a4 - a3);
+  const T s1 = mc_slope(d01, d12);
+  const T s2 = mc_slope(d12, d23);
+  const T s3 = mc_slope(d23, d34);
+  // interface offsets from a2: left = -d12/2 - (s2 - s1)/6, right = d23/2 - (s3 - s2)/6
+  T lo = T(-0.5) * d12 - (s2 - s1) * T(1.0 / 6.0);
+  T ro = T(0.5) * d23 - (s3 - s2) * T(1.0 / 6.0);
+  ppm_monotone(lo, ro);
+  l = a2 + double(lo);
+  r = a2 + double(ro);
 }
 
 // ---------------------------------------------------------------------------
-// Closure: row D of P = D E along axis DIR. D = (1-chi)/2 I + (3chi-1)/2 n n,
-// chi = Levermore M1 Eddington factor of f = |F|/(cE) (clipped to 1), or 1/3.
+// Closure, cancellation-free form. With f^2 = min(|F|^2/(cE)^2, 1) and
+// s = sqrt(4 - 3 f^2), the Levermore Eddington factor is
+//   chi = (3 + 4 f^2)/(5 + 2 s) = 1/3 + 2 f^2/(2 + s),
+// and D = (1-chi)/2 I + (3chi-1)/2 n n = I/3 + dD with
+//   dD_jk = -f^2 h delta_jk + 3 h F_j F_k r,   h = 1/(2+s), r = 1/max(|F|^2, (cE)^2).
+// Only dD (small in thick regions) goes through T.
 // ---------------------------------------------------------------------------
 template <int ND, int DIR, typename T>
-__device__ __forceinline__ void closure_row(int closure, T c, T E, const T* F, T* Drow) {
+__device__ __forceinline__ void closure_dD(int closure, double c, double E, const double* F,
+                                           T* dD) {
+  if (closure == 1) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) dD[k] = T(0);
+    return;
+  }
+  T Ft[ND];
   T F2 = T(0);
 #pragma unroll
-  for (int k = 0; k < ND; ++k) F2 += F[k] * F[k];
-  T chi;
-  if (closure == 1) {
-    chi = T(1.0 / 3.0);
-  } else {
-    const T cE = c * E;
-    const T f2 = fmin(F2 / (cE * cE), T(1));
-    chi = (T(3) + T(4) * f2) / (T(5) + T(2) * sqrt(T(4) - T(3) * f2));
+  for (int k = 0; k < ND; ++k) {
+    Ft[k] = T(F[k]);
+    F2 += Ft[k] * Ft[k];
   }
-  const T a = T(0.5) * (T(1) - chi);
-  const T b = T(0.5) * (T(3) * chi - T(1));
-  const T bn = (F2 > T(0)) ? (b / F2) * F[DIR] : T(0);
+  const T cE = T(c * E);
+  const T r = rcp(fmax(F2, cE * cE));
+  const T f2 = F2 * r;
+  const T h = rcp(T(2) + sqrt(T(4) - T(3) * f2));
+  const T g = T(3) * h * r * Ft[DIR];
 #pragma unroll
-  for (int k = 0; k < ND; ++k) Drow[k] = bn * F[k] + ((k == DIR) ? a : T(0));
+  for (int k = 0; k < ND; ++k) dD[k] = g * Ft[k] - ((k == DIR) ? f2 * h : T(0));
 }
 
 // HLL flux along DIR between edge states Um = (E, F..) and Up (RSLA form):
-// Phi_E = (chat/c) F_DIR, Phi_Fk = c chat E D_DIR,k, speed chat sqrt(max D_DIR,DIR).
+// Phi_E = (chat/c) F_DIR, Phi_Fk = c chat E D_DIR,k, signal speed
+// chat sqrt(max D_DIR,DIR) (the uncorrected speed, Sec. 4.3). The O(1) parts are
+// formed in double, the closure deviation dD in T.
 template <int ND, int DIR, typename T>
-__device__ __forceinline__ void hll_flux(int closure, T c, T chat, T chat_over_c, T c_chat,
-                                         const T* Um, const T* Up, T* fl) {
-  T Dm[ND], Dp[ND];
-  closure_row<ND, DIR, T>(closure, c, Um[0], Um + 1, Dm);
-  closure_row<ND, DIR, T>(closure, c, Up[0], Up + 1, Dp);
-  const T hS = T(0.5) * chat * sqrt(fmax(Dm[DIR], Dp[DIR]));
-  fl[0] = T(0.5) * chat_over_c * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
-  const T em = c_chat * Um[0];
-  const T ep = c_chat * Up[0];
+__device__ __forceinline__ void hll_flux(int closure, double c, double chat, double chat_over_c,
+                                         double c_chat, const double* Um, const double* Up,
+                                         double* fl) {
+  T dm[ND], dp[ND];
+  closure_dD<ND, DIR, T>(closure, c, Um[0], Um + 1, dm);
+  closure_dD<ND, DIR, T>(closure, c, Up[0], Up + 1, dp);
+  const T Ddd = T(1.0 / 3.0) + fmax(dm[DIR], dp[DIR]);
+  const double hS = 0.5 * chat * double(sqrt(Ddd));
+  fl[0] = 0.5 * chat_over_c * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
+  const T em = T(Um[0]), ep = T(Up[0]);
+  const double half_cc = 0.5 * c_chat;
 #pragma unroll
-  for (int k = 0; k < ND; ++k)
-    fl[1 + k] = T(0.5) * (em * Dm[k] + ep * Dp[k]) - hS * (Up[1 + k] - Um[1 + k]);
+  for (int k = 0; k < ND; ++k) {
+    double iso = (k == DIR) ? (Um[0] + Up[0]) * (1.0 / 3.0) : 0.0;
+    fl[1 + k] = half_cc * (iso + double(em * dm[k] + ep * dp[k])) - hS * (Up[1 + k] - Um[1 + k]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -119,24 +147,22 @@ __device__ __forceinline__ void hll_flux(int closure, T c, T chat, T chat_over_c
 template <int ND>
 __device__ __forceinline__ void closure_full(int closure, double c, double E, const double* F,
                                              double (*D)[ND]) {
-  double F2 = 0.0;
+  double g = 0.0, iso = 1.0 / 3.0;
+  if (closure != 1) {
+    double F2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < ND; ++k) F2 += F[k] * F[k];
-  double chi;
-  if (closure == 1) {
-    chi = 1.0 / 3.0;
-  } else {
+    for (int k = 0; k < ND; ++k) F2 += F[k] * F[k];
     const double cE = c * E;
-    const double f2 = fmin(F2 / (cE * cE), 1.0);
-    chi = (3.0 + 4.0 * f2) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f2));
+    const double r = rcp(fmax(F2, cE * cE));
+    const double f2 = F2 * r;
+    const double h = rcp(2.0 + sqrt(4.0 - 3.0 * f2));
+    g = 3.0 * h * r;
+    iso -= f2 * h;
   }
-  const double a = 0.5 * (1.0 - chi);
-  const double b = 0.5 * (3.0 * chi - 1.0);
-  const double bi = (F2 > 0.0) ? b / F2 : 0.0;
 #pragma unroll
   for (int j = 0; j < ND; ++j)
 #pragma unroll
-    for (int k = 0; k < ND; ++k) D[j][k] = bi * F[j] * F[k] + ((j == k) ? a : 0.0);
+    for (int k = 0; k < ND; ++k) D[j][k] = g * F[j] * F[k] + ((j == k) ? iso : 0.0);
 }
 
 template <int ND>
@@ -149,9 +175,9 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   const double c = P.c, ch = P.chat;
   const double k_cc = P.c_over_chat;
   const double Cv = rho * P.cv_mass;
-  const double inv_Cv = 1.0 / Cv;
-  const double inv_rho = 1.0 / rho;
-  const double inv_tch = 1.0 / (tau * ch);
+  const double inv_Cv = rcp(Cv);
+  const double inv_rho = rcp(rho);
+  const double inv_tch = rcp(tau * ch);
   const double ar = P.a_r;
 
   const double E0 = E, Eg0 = Eg;
@@ -168,8 +194,8 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   double R = 0.0;
   const double tol = P.newton_rtol * (Eg0 + k_cc * E0);
   // dF_R/dR of the simplified Jacobian; fixed for the call
-  const double J22 = -1.0 / (ch * chiE * tau) - 1.0;
-  const double J21c = 4.0 * chiP * ar / (chiE * Cv);
+  const double J22 = -rcp(ch * chiE * tau) - 1.0;
+  const double J21c = 4.0 * chiP * ar * rcp(chiE * Cv);
   const double ctau = ch * tau;
 
   double Enew = E0, Fnew[ND], Pnew[ND];
@@ -204,7 +230,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     const bool o2 = (P.v_order == 2);
     const double Afac = o2 ? 1.0 + 0.5 * b2 : 1.0;
     const double B = o2 ? chiE * (1.0 + 0.5 * b2) - (chiF - chiE) * (b2 + vDv * P.inv_c2) : chiE;
-    const double inv_B = 1.0 / B;
+    const double inv_B = rcp(B);
     const double Cc = (2.0 * chiE - chiF) * vF * P.inv_c2;
     const double Aco = chiP * ar * Afac;
 
@@ -222,7 +248,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       }
       if (it >= P.newton_maxit) break;
       const double J21 = J21c * T2 * T;
-      const double inv_det = 1.0 / (J22 - k_cc * J21);
+      const double inv_det = rcp(J22 - k_cc * J21);
       Egas += (k_cc * FR - J22 * FG) * inv_det;
       R += (J21 * FG - FR) * inv_det;
     }
@@ -236,7 +262,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     const double Tn = (Egas - KE) * inv_Cv;
     const double Tn2 = Tn * Tn;
     const double Bn = ar * Tn2 * Tn2;
-    const double inv_den = o2 ? 1.0 / (1.0 + ctau * chiF * (1.0 + 0.5 * b2)) : 1.0 / (1.0 + ctau * chiF);
+    const double inv_den = rcp(o2 ? 1.0 + ctau * chiF * (1.0 + 0.5 * b2) : 1.0 + ctau * chiF);
     const double xv = chiP * Bn + (o2 ? 0.0 : (chiF - chiE) * Enew);
     double vnew[ND];
     double v2n = 0.0;

@@ -73,9 +73,11 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   constexpr int AREA = (NTILE > NFX + NFY) ? NTILE : NFX + NFY;
   constexpr int NEYs = NEY > 0 ? NEY : 1;
 
-  __shared__ TT s_area[NR][AREA];            // (E, F) tile, then face fluxes
-  __shared__ TT s_exL[NR][NEX], s_exR[NR][NEX];
-  __shared__ TT s_eyL[NR][NEYs], s_eyR[NR][NEYs];
+  // LDS holds values, edge states and fluxes in double; TT is the arithmetic
+  // type of the limiter and closure (delta form, see rhd_device.hpp).
+  __shared__ double s_area[NR][AREA];        // (E, F) tile, then face fluxes
+  __shared__ double s_exL[NR][NEX], s_exR[NR][NEX];
+  __shared__ double s_eyL[NR][NEYs], s_eyR[NR][NEYs];
 
   const int tid = threadIdx.x;
   const int tx = tid % TX;
@@ -87,19 +89,25 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   const int z1 = min(z0 + zchunk, nz);
   const int gx = x0 + tx, gy = y0 + ty;
   const bool valid = (gx < nx) && (gy < ny);
-  bool fl_;
-  const int cx = ghost(gx, nx, P.bc[0], fl_);   // in-range column for loads
-  const int cy = (ND >= 2) ? ghost(gy, ny, P.bc[1], fl_) : 0;
+  // In-range source column of this thread. Threads of a ragged last tile sit
+  // past the grid edge; their column then acts as a ghost cell of the tile and
+  // takes the ghost rule (including the sign flip of the normal flux).
+  bool own_fx = false, own_fy = false;
+  const int cx = ghost(gx, nx, P.bc[0], own_fx);
+  const int cy = (ND >= 2) ? ghost(gy, ny, P.bc[1], own_fy) : 0;
   const long long N = P.N;
 
-  const TT c = TT(P.c), ch = TT(P.chat), chc = TT(P.chat_over_c), cch = TT(P.c_chat);
+  const double c = P.c, ch = P.chat, chc = P.chat_over_c, cch = P.c_chat;
   const int clo = P.closure;
 
   // ---- z pipeline state (ND == 3) ----
-  TT zv1[NR], zv2[NR], zdm[NR], zI[NR], zaR[NR], zc[NR];
-  TT zfl_prev[NR];
+  // a_k, a_{k+1}, a_{k+2}; limited slope of cell k+1; raw left interface of
+  // cell k+1 (offset from a_{k+1}); monotonised right edge of cell k; z-flux at
+  // face k-1/2.
+  double zc[NR], zv1[NR], zv2[NR], zaR[NR], zfl_prev[NR];
+  TT zs[NR], zIo[NR];
   if constexpr (ND == 3) {
-    TT w[6][NR];
+    double w[6][NR];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       bool flip;
@@ -107,56 +115,54 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       const long long q = cidx(P, cx, cy, gz);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        TT val = TT(ys[r * N + q]);
+        const double val = ys[r * N + q];
         w[m][r] = (flip && r == 3) ? -val : val;
       }
     }
+    double Um[NR], Up[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const TT dA = mc_slope(w[0][r], w[1][r], w[2][r]);   // z0-2
-      const TT dB = mc_slope(w[1][r], w[2][r], w[3][r]);   // z0-1
-      const TT dC = mc_slope(w[2][r], w[3][r], w[4][r]);   // z0
-      const TT dD = mc_slope(w[3][r], w[4][r], w[5][r]);   // z0+1
-      TT Im = ppm_iface(w[1][r], w[2][r], dA, dB);         // z0-3/2
-      TT I0 = ppm_iface(w[2][r], w[3][r], dB, dC);         // z0-1/2
-      TT Ip = ppm_iface(w[3][r], w[4][r], dC, dD);         // z0+1/2
-      TT lm = Im, rm = I0;
-      ppm_monotone(w[2][r], lm, rm);                       // cell z0-1
-      TT l0 = I0, r0 = Ip;
-      ppm_monotone(w[3][r], l0, r0);                       // cell z0
-      zaR[r] = r0;
-      zI[r] = Ip;
-      zdm[r] = dD;
+      const TT d01 = TT(w[1][r] - w[0][r]), d12 = TT(w[2][r] - w[1][r]);
+      const TT d23 = TT(w[3][r] - w[2][r]), d34 = TT(w[4][r] - w[3][r]);
+      const TT d45 = TT(w[5][r] - w[4][r]);
+      const TT sA = mc_slope(d01, d12);   // cell z0-2
+      const TT sB = mc_slope(d12, d23);   // cell z0-1
+      const TT sC = mc_slope(d23, d34);   // cell z0
+      const TT sD = mc_slope(d34, d45);   // cell z0+1
+      TT lm = TT(-0.5) * d12 - (sB - sA) * TT(1.0 / 6.0);
+      TT rm = TT(0.5) * d23 - (sC - sB) * TT(1.0 / 6.0);
+      ppm_monotone(lm, rm);               // cell z0-1
+      TT l0 = TT(-0.5) * d23 - (sC - sB) * TT(1.0 / 6.0);
+      TT r0 = TT(0.5) * d34 - (sD - sC) * TT(1.0 / 6.0);
+      ppm_monotone(l0, r0);               // cell z0
+      Um[r] = w[2][r] + double(rm);
+      Up[r] = w[3][r] + double(l0);
+      zaR[r] = w[3][r] + double(r0);
+      zIo[r] = TT(-0.5) * d34 - (sD - sC) * TT(1.0 / 6.0);
+      zs[r] = sD;
       zc[r] = w[3][r];
       zv1[r] = w[4][r];
       zv2[r] = w[5][r];
-      w[0][r] = rm;   // reuse as the z0-1/2 face states
-      w[1][r] = l0;
-    }
-    TT Um[NR], Up[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      Um[r] = w[0][r];
-      Up[r] = w[1][r];
     }
     hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, Um, Up, zfl_prev);
   }
 
   for (int k = z0; k < z1; ++k) {
     // ---------------- stage the plane's (E, F) tile in LDS ----------------
-    TT own[NR];
+    double own[NR];
     if constexpr (ND == 3) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) own[r] = zc[r];
     } else {
       const long long q = cidx(P, cx, cy, k);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) own[r] = TT(ys[r * N + q]);
+      for (int r = 0; r < NR; ++r) own[r] = ys[r * N + q];
     }
     {
       const int t = (ty + (ND >= 2 ? HALO : 0)) * TW + tx + HALO;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) s_area[r][t] = own[r];
+      for (int r = 0; r < NR; ++r)
+        s_area[r][t] = ((own_fx && r == 1) || (own_fy && r == 2)) ? -own[r] : own[r];
     }
     // halo: 3 columns left and right of every row; 3 rows above and below
     constexpr int NHX = 2 * HALO * TY;
@@ -179,7 +185,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       const long long q = cidx(P, sx, sy, k);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        TT val = TT(ys[r * N + q]);
+        double val = ys[r * N + q];
         if ((fx && r == 1) || (fy && r == 2)) val = -val;
         s_area[r][ly * TW + lx] = val;
       }
@@ -193,9 +199,9 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
         const int base = (row + (ND >= 2 ? HALO : 0)) * TW + col;  // = centre - 2
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const TT* a = &s_area[r][base];
-          TT l, rr;
-          ppm_edges5(a[0], a[1], a[2], a[3], a[4], l, rr);
+          const double* a = &s_area[r][base];
+          double l, rr;
+          ppm_edges5<TT>(a[0], a[1], a[2], a[3], a[4], l, rr);
           s_exL[r][e] = l;
           s_exR[r][e] = rr;
         }
@@ -205,9 +211,9 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
         const int base = row * TW + col + HALO;              // = centre - 2 rows
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const TT* a = &s_area[r][base];
-          TT l, rr;
-          ppm_edges5(a[0], a[TW], a[2 * TW], a[3 * TW], a[4 * TW], l, rr);
+          const double* a = &s_area[r][base];
+          double l, rr;
+          ppm_edges5<TT>(a[0], a[TW], a[2 * TW], a[3 * TW], a[4 * TW], l, rr);
           s_eyL[r][e2] = l;
           s_eyR[r][e2] = rr;
         }
@@ -217,7 +223,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
 
     // ---------------- HLL fluxes, once per face (into the tile's LDS) -------
     for (int f = tid; f < NFX + NFY; f += NTHREADS) {
-      TT Um[NR], Up[NR], fl[NR];
+      double Um[NR], Up[NR], fl[NR];
       if (f < NFX) {
         const int row = f / (TX + 1), fx = f % (TX + 1);     // between cells fx-1 | fx
         const int eb = row * (TX + 2) + fx;
@@ -251,29 +257,33 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       bool flip;
       const int gz = ghost(k + 3, nz, P.bc[2], flip);
       const long long q = cidx(P, cx, cy, gz);
-      TT aL1[NR], aR1[NR], fz[NR];
+      double aL1[NR], fz[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        TT w3 = TT(ys[r * N + q]);
+        double w3 = ys[r * N + q];
         if (flip && r == 3) w3 = -w3;
-        const TT d2 = mc_slope(zv1[r], zv2[r], w3);
-        const TT I2 = ppm_iface(zv1[r], zv2[r], zdm[r], d2);
-        TT l = zI[r], rr = I2;
-        ppm_monotone(zv1[r], l, rr);
-        aL1[r] = l;
-        aR1[r] = rr;
-        zI[r] = I2;
-        zdm[r] = d2;
+        const TT d12 = TT(zv2[r] - zv1[r]);
+        const TT d23 = TT(w3 - zv2[r]);
+        const TT s2 = mc_slope(d12, d23);                       // cell k+2
+        TT lo = zIo[r];
+        TT ro = TT(0.5) * d12 - (s2 - zs[r]) * TT(1.0 / 6.0);   // cell k+1
+        zIo[r] = TT(-0.5) * d12 - (s2 - zs[r]) * TT(1.0 / 6.0); // left of cell k+2
+        ppm_monotone(lo, ro);
+        aL1[r] = zv1[r] + double(lo);
+        const double aR1 = zv1[r] + double(ro);
+        zs[r] = s2;
         zc[r] = zv1[r];
         zv1[r] = zv2[r];
         zv2[r] = w3;
+        fz[r] = aR1;   // kept until the flux below is formed
       }
-      hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, zaR, aL1, fz);
+      double fl3[NR];
+      hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, zaR, aL1, fl3);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        divz[r] = double(fz[r]) - double(zfl_prev[r]);
-        zfl_prev[r] = fz[r];
-        zaR[r] = aR1[r];
+        divz[r] = fl3[r] - zfl_prev[r];
+        zfl_prev[r] = fl3[r];
+        zaR[r] = fz[r];
       }
     }
     __syncthreads();
@@ -282,9 +292,9 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      double d = double(s_area[r][ty * (TX + 1) + tx + 1]) - double(s_area[r][ty * (TX + 1) + tx]);
+      double d = s_area[r][ty * (TX + 1) + tx + 1] - s_area[r][ty * (TX + 1) + tx];
       if constexpr (ND >= 2)
-        d += double(s_area[r][NFX + (ty + 1) * TX + tx]) - double(s_area[r][NFX + ty * TX + tx]);
+        d += s_area[r][NFX + (ty + 1) * TX + tx] - s_area[r][NFX + ty * TX + tx];
       d += divz[r];
       s[r] = -d * P.inv_dx;
     }
