@@ -1,0 +1,587 @@
+// Adjoint (reverse-mode derivative) of the PD-ARS radiation step, gfx950.
+//
+// For one step (stage s(y) = transport, Src = local implicit source):
+//   stage 1: t1 = y^n + dt s(y^n),                 h = Src(t1; dt)
+//   stage 2: t2 = (y^n + h)/2 + dt/2 s(h),          y^{n+1} = Src(t2; dt/2)
+// the reverse sweep given lambda = dJ/dy^{n+1} is
+//   mu2 = Src adjoint at y^{n+1};  lh = mu2/2 + (dt/2) s'(h)^T mu2;  ln = mu2/2
+//   mu1 = Src adjoint at h on lh;   ln += mu1 + dt s'(y^n)^T mu1.
+//
+// Src adjoint (implicit function theorem at the converged state z of the local
+// system r(z) = z - z_in - tau f(z; kappa) = 0, f the mixed-frame four-force
+// terms of eq. G0-G1 in RSLA form, eq. egupdate-fupdate): with A = I - tau df/dz,
+//   lambda_in = A^{-T} lambda_out,   dJ/dkappa += tau (df/dkappa)^T lambda_in.
+// df/dz and df/dkappa are exact: f is evaluated in forward-mode dual numbers
+// seeded along each unknown. The fixed point of the paper's inner/outer iteration
+// is the solution of r(z) = 0 with the closure tensor evaluated at z, so this is
+// the derivative of what the forward step computes (to the outer tolerance).
+//
+// Transport adjoint s'(y)^T lambda (gather form, no atomics), per axis d:
+//   1. per face i+1/2: phi = dJ/dPhi = (lambda_{i+1} - lambda_i)/dx, and the
+//      adjoints of its two edge states mu-/mu+ = (dPhi/dU-/+)^T phi (dual seeds);
+//   2. per cell i: PPM partials of its edge states w.r.t. the 5 stencil values
+//      (5-tangent duals) times mu- of face i+1/2 and mu+ of face i-1/2, giving
+//      its contribution to each of the cells i-2..i+2;
+//   3. per cell j: sum of the contributions addressed to j.
+// Periodic axes only (the library rejects reflecting axes for the adjoint).
+#include "rhd_device.hpp"
+
+namespace rhd {
+
+constexpr int ATHREADS = 256;
+
+// ---------------------------------------------------------------------------
+// Scalar types: double, a one-tangent dual, and a five-tangent dual.
+// Comparisons, min/max and sign decisions use the value only.
+// ---------------------------------------------------------------------------
+struct Dd {
+  double v, d;
+};
+template <typename S> __device__ __forceinline__ S mk0(double x);
+template <> __device__ __forceinline__ double mk0<double>(double x) { return x; }
+template <> __device__ __forceinline__ Dd mk0<Dd>(double x) { return Dd{x, 0.0}; }
+__device__ __forceinline__ Dd mk(double v, double d = 0.0) { return Dd{v, d}; }
+__device__ __forceinline__ Dd operator+(Dd a, Dd b) { return mk(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dd operator-(Dd a, Dd b) { return mk(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dd operator-(Dd a) { return mk(-a.v, -a.d); }
+__device__ __forceinline__ Dd operator*(Dd a, Dd b) { return mk(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ Dd operator*(double a, Dd b) { return mk(a * b.v, a * b.d); }
+__device__ __forceinline__ Dd operator*(Dd a, double b) { return mk(a.v * b, a.d * b); }
+__device__ __forceinline__ Dd operator+(Dd a, double b) { return mk(a.v + b, a.d); }
+__device__ __forceinline__ Dd operator+(double a, Dd b) { return mk(a + b.v, b.d); }
+__device__ __forceinline__ Dd operator-(double a, Dd b) { return mk(a - b.v, -b.d); }
+__device__ __forceinline__ Dd operator-(Dd a, double b) { return mk(a.v - b, a.d); }
+__device__ __forceinline__ Dd operator/(Dd a, Dd b) {
+  const double q = a.v / b.v;
+  return mk(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ Dd operator/(double a, Dd b) {
+  const double q = a / b.v;
+  return mk(q, -q * b.d / b.v);
+}
+__device__ __forceinline__ Dd dsqrt(Dd a) {
+  const double s = sqrt(a.v);
+  return mk(s, s > 0.0 ? a.d / (2.0 * s) : 0.0);
+}
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double vof(double a) { return a; }
+__device__ __forceinline__ double vof(Dd a) { return a.v; }
+template <typename S> __device__ __forceinline__ S smax(S a, S b) { return vof(a) < vof(b) ? b : a; }
+template <typename S> __device__ __forceinline__ S sabs(S a) { return vof(a) < 0.0 ? -a : a; }
+
+struct D5 {
+  double v, d[5];
+};
+__device__ __forceinline__ D5 operator+(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v + b.v;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r.d[i] = a.d[i] + b.d[i];
+  return r;
+}
+__device__ __forceinline__ D5 operator-(const D5& a, const D5& b) {
+  D5 r;
+  r.v = a.v - b.v;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r.d[i] = a.d[i] - b.d[i];
+  return r;
+}
+__device__ __forceinline__ D5 operator-(const D5& a) {
+  D5 r;
+  r.v = -a.v;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r.d[i] = -a.d[i];
+  return r;
+}
+__device__ __forceinline__ D5 operator*(double a, const D5& b) {
+  D5 r;
+  r.v = a * b.v;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r.d[i] = a * b.d[i];
+  return r;
+}
+__device__ __forceinline__ double vof(const D5& a) { return a.v; }
+__device__ __forceinline__ D5 d5zero() {
+  D5 r;
+  r.v = 0.0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r.d[i] = 0.0;
+  return r;
+}
+
+// PPM (same method as the forward) on a piecewise-linear scalar type: the
+// tangents of the active branch are carried along.
+template <typename S>
+__device__ __forceinline__ S slope_s(S dl, S dr, S zero) {
+  const S dc = 0.5 * (dl + dr);
+  if (!(vof(dl) * vof(dr) > 0.0)) return zero;
+  const double adc = fabs(vof(dc)), adl = 2.0 * fabs(vof(dl)), adr = 2.0 * fabs(vof(dr));
+  S m;
+  if (adc <= adl && adc <= adr) {
+    m = sabs(dc);
+  } else if (adl <= adr) {
+    m = 2.0 * sabs(dl);
+  } else {
+    m = 2.0 * sabs(dr);
+  }
+  return vof(dc) < 0.0 ? -m : m;
+}
+__device__ __forceinline__ D5 sabs(const D5& a) { return a.v < 0.0 ? -a : a; }
+
+// edge offsets (from the middle value) of the middle cell of a0..a4
+template <typename S>
+__device__ __forceinline__ void ppm_edges_s(const S& a0, const S& a1, const S& a2, const S& a3,
+                                            const S& a4, S& l, S& r, S zero) {
+  const S d01 = a1 - a0, d12 = a2 - a1, d23 = a3 - a2, d34 = a4 - a3;
+  const S s1 = slope_s(d01, d12, zero), s2 = slope_s(d12, d23, zero), s3 = slope_s(d23, d34, zero);
+  S lo = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
+  S ro = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
+  if (vof(ro) * vof(lo) >= 0.0) {
+    lo = zero;
+    ro = zero;
+  } else {
+    const double del = vof(ro) - vof(lo);
+    const double a6 = -3.0 * (vof(lo) + vof(ro));
+    if (del * a6 > del * del) {
+      lo = (-2.0) * ro;
+    } else if (del * a6 < -(del * del)) {
+      ro = (-2.0) * lo;
+    }
+  }
+  l = a2 + lo;
+  r = a2 + ro;
+}
+
+// HLL flux along DIR on a generic scalar type (same formulas as the forward).
+template <int ND, int DIR, typename S>
+__device__ void hll_flux_s(const DevParams& P, const S* Um, const S* Up, S* fl) {
+  S Dm[ND], Dp[ND];
+  auto row = [&](const S* U, S* Dr) {
+    if (P.closure == 1) {
+#pragma unroll
+      for (int k = 0; k < ND; ++k) Dr[k] = (k == DIR) ? mk0<S>(1.0 / 3.0) : mk0<S>(0.0);
+      return;
+    }
+    S F2 = mk0<S>(0.0);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) F2 = F2 + U[1 + k] * U[1 + k];
+    const S cE = P.c * U[0];
+    const S r = 1.0 / smax(F2, cE * cE);
+    const S f2 = F2 * r;
+    const S h = 1.0 / (2.0 + dsqrt(4.0 - 3.0 * f2));
+    const S g = 3.0 * h * r * U[1 + DIR];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) Dr[k] = g * U[1 + k] + ((k == DIR) ? (1.0 / 3.0) - f2 * h : mk0<S>(0.0));
+  };
+  row(Um, Dm);
+  row(Up, Dp);
+  const S hS = (0.5 * P.chat) * dsqrt(smax(Dm[DIR], Dp[DIR]));
+  fl[0] = (0.5 * P.chat_over_c) * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
+#pragma unroll
+  for (int k = 0; k < ND; ++k)
+    fl[1 + k] = (0.5 * P.c_chat) * (Um[0] * Dm[k] + Up[0] * Dp[k]) - hS * (Up[1 + k] - Um[1 + k]);
+}
+
+// The mixed-frame source terms f(z) (per cell), z = (E, F_1..F_ND, E_gas, p_1..p_ND):
+// f_E = (chat/c)(-c G0), f_F = chat c (-G), f_Egas = c G0, f_p = G, with -c G0 and
+// -G from eq. G0-G1 (order 2; order 1 keeps the O(v/c) terms), P = D(E, F) E.
+template <int ND, typename S>
+__device__ void source_rhs(const DevParams& P, const S* z, S rho, S kP, S kF, S* f) {
+  const double c = P.c;
+  const S chiP = rho * kP, chiE = chiP, chiF = rho * kF;
+  const S E = z[0], Eg = z[1 + ND];
+  S v[ND];
+  S v2 = mk0<S>(0.0), vF = mk0<S>(0.0), F2 = mk0<S>(0.0);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    v[k] = z[2 + ND + k] / rho;
+    v2 = v2 + v[k] * v[k];
+    vF = vF + v[k] * z[1 + k];
+    F2 = F2 + z[1 + k] * z[1 + k];
+  }
+  const S b2 = v2 * P.inv_c2;
+  const S T = (Eg - 0.5 * rho * v2) / (rho * P.cv_mass);
+  const S T2 = T * T;
+  const S B = P.a_r * (T2 * T2);
+  S g = mk0<S>(0.0), iso = mk0<S>(1.0 / 3.0);
+  if (P.closure != 1) {
+    const S cE = c * E;
+    const S r = 1.0 / smax(F2, cE * cE);
+    const S f2 = F2 * r;
+    const S h = 1.0 / (2.0 + dsqrt(4.0 - 3.0 * f2));
+    g = 3.0 * h * r;
+    iso = (1.0 / 3.0) - f2 * h;
+  }
+  S Dv[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) Dv[k] = iso * v[k] + g * z[1 + k] * vF;
+  const S vDv = iso * v2 + g * vF * vF;
+  S mcG0, mG[ND];
+  if (P.v_order == 2) {
+    const S hb = 1.0 + 0.5 * b2;
+    mcG0 = c * (chiP * B - chiE * E) * hb + (2.0 * chiE - chiF) * vF * (1.0 / c) +
+           c * (chiF - chiE) * (b2 * E + E * vDv * P.inv_c2);
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+      mG[k] = (-1.0 / c) * chiF * z[1 + k] * hb + (1.0 / c) * chiP * B * v[k] +
+              (1.0 / c) * chiF * E * Dv[k] +
+              (1.0 / c) * (chiF - chiE) * (E - 2.0 * vF * P.inv_c2) * v[k];
+  } else {
+    mcG0 = c * (chiP * B - chiE * E) + (2.0 * chiE - chiF) * vF * (1.0 / c);
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+      mG[k] = (-1.0 / c) * chiF * z[1 + k] + (1.0 / c) * chiP * B * v[k] +
+              (1.0 / c) * chiF * E * Dv[k] + (1.0 / c) * (chiF - chiE) * E * v[k];
+  }
+  f[0] = P.chat_over_c * mcG0;
+  f[1 + ND] = -mcG0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    f[1 + k] = P.c_chat * mG[k];
+    f[2 + ND + k] = -mG[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long nbr(const DevParams& P, long long q, int dir, int off) {
+  // periodic neighbour of cell q at offset off along axis dir
+  const long long nx = P.n[0], ny = P.n[1], nz = P.n[2];
+  long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+  if (dir == 0) {
+    x = ((x + off) % nx + nx) % nx;
+  } else if (dir == 1) {
+    y = ((y + off) % ny + ny) % ny;
+  } else {
+    z = ((z + off) % nz + nz) % nz;
+  }
+  return (z * ny + y) * nx + x;
+}
+
+// Src adjoint: lam <- A^{-T} lam at the converged cell state z; g_kappa += tau (df/dkappa)^T lam.
+template <int ND>
+__global__ void __launch_bounds__(ATHREADS)
+k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
+          const double* __restrict__ rho, const double* __restrict__ kP,
+          const double* __restrict__ kF, double tau, double* gkP, double* gkF) {
+  constexpr int M = 2 + 2 * ND;
+  const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
+  if (q >= P.N) return;
+  const long long N = P.N;
+  double z[M], lv[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    z[j] = zs[j * N + q];
+    lv[j] = lam[j * N + q];
+  }
+  const double rq = rho[q], kp = kP[q], kf = P.kF_alias ? kp : kF[q];
+  if (rq * kp == 0.0 && rq * kf == 0.0) return;   // source is the identity there
+
+  // scales of the unknowns (conditioning of the dense solve)
+  double sc[M];
+  {
+    double F2 = 0.0, p2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      F2 += z[1 + k] * z[1 + k];
+      p2 += z[2 + ND + k] * z[2 + ND + k];
+    }
+    const double sE = fabs(z[0]) > 0.0 ? fabs(z[0]) : 1.0;
+    const double sF = fmax(sqrt(F2), 1e-6 * P.c * sE);
+    const double sP = fmax(sqrt(p2), sF * P.inv_c_chat);
+    sc[0] = sE;
+    sc[1 + ND] = fabs(z[1 + ND]) > 0.0 ? fabs(z[1 + ND]) : 1.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      sc[1 + k] = sF;
+      sc[2 + ND + k] = sP;
+    }
+  }
+  // Mt = (S^-1 A S)^T, A = I - tau df/dz
+  double Mt[M][M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    Dd zd[M], fd[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) zd[i] = mk(z[i], i == j ? 1.0 : 0.0);
+    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), fd);
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+      Mt[j][i] = ((i == j) ? 1.0 : 0.0) - tau * fd[i].d * sc[j] / sc[i];
+  }
+  // solve Mt muhat = S lam (partial pivoting, fully unrolled: no dynamic indexing)
+  double b[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) b[i] = sc[i] * lv[i];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    int p = k;
+    double best = fabs(Mt[k][k]);
+#pragma unroll
+    for (int i = k + 1; i < M; ++i) {
+      const double a = fabs(Mt[i][k]);
+      if (a > best) {
+        best = a;
+        p = i;
+      }
+    }
+#pragma unroll
+    for (int i = k + 1; i < M; ++i) {
+      if (i == p) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const double t = Mt[k][j];
+          Mt[k][j] = Mt[i][j];
+          Mt[i][j] = t;
+        }
+        const double t = b[k];
+        b[k] = b[i];
+        b[i] = t;
+      }
+    }
+    const double inv = 1.0 / Mt[k][k];
+#pragma unroll
+    for (int i = k + 1; i < M; ++i) {
+      const double m = Mt[i][k] * inv;
+#pragma unroll
+      for (int j = k + 1; j < M; ++j) Mt[i][j] -= m * Mt[k][j];
+      b[i] -= m * b[k];
+    }
+  }
+  double mu[M];
+#pragma unroll
+  for (int i = M - 1; i >= 0; --i) {
+    double acc = b[i];
+#pragma unroll
+    for (int j = i + 1; j < M; ++j) acc -= Mt[i][j] * mu[j];
+    mu[i] = acc / Mt[i][i];
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) mu[i] /= sc[i];   // unscale
+
+  // dJ/dkappa: tau (df/dkappa)^T mu
+  Dd zd[M], fd[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) zd[i] = mk(z[i]);
+  if (P.kF_alias) {
+    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kp, gkF ? 0.0 : 1.0), fd);
+    double g = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) g += fd[i].d * mu[i];
+    gkP[q] += tau * g;
+    if (gkF) {
+      source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kp, 1.0), fd);
+      double h = 0.0;
+#pragma unroll
+      for (int i = 0; i < M; ++i) h += fd[i].d * mu[i];
+      gkF[q] += tau * h;
+    }
+  } else {
+    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kf), fd);
+    double g = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) g += fd[i].d * mu[i];
+    gkP[q] += tau * g;
+    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf, 1.0), fd);
+    double h = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) h += fd[i].d * mu[i];
+    if (gkF) gkF[q] += tau * h; else gkP[q] += tau * h;
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) lam[i * N + q] = mu[i];
+}
+
+// Face adjoint along DIR: for face i+1/2 (owned by cell i), fm[0..NR) = (dPhi/dU-)^T phi,
+// fm[NR..2NR) = (dPhi/dU+)^T phi with phi = scale (lam_{i+1} - lam_i)/dx.
+template <int ND, int DIR>
+__global__ void __launch_bounds__(ATHREADS)
+k_face_adj(DevParams P, const double* __restrict__ y, const double* __restrict__ lam, double scale,
+           double* __restrict__ fm) {
+  constexpr int NR = 1 + ND;
+  const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
+  if (q >= P.N) return;
+  const long long N = P.N;
+  long long nb[6];
+#pragma unroll
+  for (int o = 0; o < 6; ++o) nb[o] = nbr(P, q, DIR, o - 2);   // cells i-2..i+3
+  double phi[NR], Um[NR], Up[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    phi[r] = scale * (lam[r * N + nb[3]] - lam[r * N + nb[2]]) * P.inv_dx;
+    double a[6];
+#pragma unroll
+    for (int o = 0; o < 6; ++o) a[o] = y[r * N + nb[o]];
+    double l, rr;
+    ppm_edges_s<double>(a[0], a[1], a[2], a[3], a[4], l, rr, 0.0);
+    Um[r] = rr;                                   // right edge of cell i
+    ppm_edges_s<double>(a[1], a[2], a[3], a[4], a[5], l, rr, 0.0);
+    Up[r] = l;                                    // left edge of cell i+1
+  }
+#pragma unroll
+  for (int j = 0; j < 2 * NR; ++j) {
+    Dd um[NR], up[NR], fl[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      um[r] = mk(Um[r], (j == r) ? 1.0 : 0.0);
+      up[r] = mk(Up[r], (j == NR + r) ? 1.0 : 0.0);
+    }
+    hll_flux_s<ND, DIR, Dd>(P, um, up, fl);
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc += phi[r] * fl[r].d;
+    fm[j * N + q] = acc;
+  }
+}
+
+// PPM adjoint along DIR: contributions of cell i to the stencil cells i-2..i+2,
+// C[(o+2) NR + r] = d aR_i/d a_{i+o} mu-_{i+1/2} + d aL_i/d a_{i+o} mu+_{i-1/2}.
+template <int ND, int DIR>
+__global__ void __launch_bounds__(ATHREADS)
+k_ppm_adj(DevParams P, const double* __restrict__ y, const double* __restrict__ fm,
+          double* __restrict__ C) {
+  constexpr int NR = 1 + ND;
+  const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
+  if (q >= P.N) return;
+  const long long N = P.N;
+  long long nb[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) nb[o] = nbr(P, q, DIR, o - 2);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const double mum = fm[r * N + q];            // face i+1/2, w.r.t. aR of cell i
+    const double mup = fm[(NR + r) * N + nb[1]]; // face i-1/2 (owned by cell i-1), w.r.t. aL of cell i
+    D5 a[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) {
+      a[o] = d5zero();
+      a[o].v = y[r * N + nb[o]];
+      a[o].d[o] = 1.0;
+    }
+    D5 l, rr;
+    ppm_edges_s<D5>(a[0], a[1], a[2], a[3], a[4], l, rr, d5zero());
+#pragma unroll
+    for (int o = 0; o < 5; ++o) C[(o * NR + r) * N + q] = rr.d[o] * mum + l.d[o] * mup;
+  }
+}
+
+// Gather: out[r][j] += sum_o C[(o+2) NR + r][j - o], o = -2..2.
+template <int ND, int DIR>
+__global__ void __launch_bounds__(ATHREADS)
+k_gather_adj(DevParams P, const double* __restrict__ C, double* __restrict__ out) {
+  constexpr int NR = 1 + ND;
+  const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
+  if (q >= P.N) return;
+  const long long N = P.N;
+  long long src[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) src[o] = nbr(P, q, DIR, -(o - 2));
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double acc = 0.0;
+#pragma unroll
+    for (int o = 0; o < 5; ++o) acc += C[(o * NR + r) * N + src[o]];
+    out[r * N + q] += acc;
+  }
+}
+
+// out = a x (+ b out)
+__global__ void __launch_bounds__(ATHREADS)
+k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * ATHREADS + threadIdx.x;
+  if (i >= n) return;
+  out[i] = a * x[i] + (b == 0.0 ? 0.0 : b * out[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Host driver of one segment (called by rhd_step_adjoint).
+// ---------------------------------------------------------------------------
+static unsigned blocks_for(long long n) { return (unsigned)((n + ATHREADS - 1) / ATHREADS); }
+
+template <int ND>
+static hipError_t transport_vjp(const DevParams& P, const double* y, const double* lam, double scale,
+                                double* out, double* fm, double* C, hipStream_t s) {
+  const unsigned nb = blocks_for(P.N);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    switch (d) {
+      case 0:
+        hipLaunchKernelGGL((k_face_adj<ND, 0>), dim3(nb), dim3(ATHREADS), 0, s, P, y, lam, scale, fm);
+        hipLaunchKernelGGL((k_ppm_adj<ND, 0>), dim3(nb), dim3(ATHREADS), 0, s, P, y, fm, C);
+        hipLaunchKernelGGL((k_gather_adj<ND, 0>), dim3(nb), dim3(ATHREADS), 0, s, P, C, out);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_face_adj<ND, (ND > 1 ? 1 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, lam, scale, fm);
+        hipLaunchKernelGGL((k_ppm_adj<ND, (ND > 1 ? 1 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, fm, C);
+        hipLaunchKernelGGL((k_gather_adj<ND, (ND > 1 ? 1 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, C, out);
+        break;
+      default:
+        hipLaunchKernelGGL((k_face_adj<ND, (ND > 2 ? 2 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, lam, scale, fm);
+        hipLaunchKernelGGL((k_ppm_adj<ND, (ND > 2 ? 2 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, fm, C);
+        hipLaunchKernelGGL((k_gather_adj<ND, (ND > 2 ? 2 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, C, out);
+        break;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int ND>
+static hipError_t adjoint_nd(const AdjointArgs& A) {
+  const DevParams& P = A.P;
+  const long long N = P.N;
+  const int nv = 2 + 2 * ND;
+  const long long M = (long long)nv * N;
+  hipStream_t s = A.stream;
+  hipError_t e;
+  auto Y = [&](int n) { return A.states + (long long)n * M; };                 // y^n, n = 0..k
+  auto H = [&](int n) { return A.states + (long long)(A.nsteps + 1 + n) * M; }; // y^{n+1/2}
+  // forward recompute of the segment
+  e = hipMemcpyAsync(Y(0), A.state0, M * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  for (int n = 0; n < A.nsteps; ++n) {
+    e = launch_stage(P, MODE_STAGE1, A.mixed, Y(n), Y(n), H(n), A.rho, A.kP, A.kF, A.dt, A.err, s);
+    if (e != hipSuccess) return e;
+    e = launch_stage(P, MODE_STAGE2, A.mixed, H(n), Y(n), Y(n + 1), A.rho, A.kP, A.kF, A.dt, A.err, s);
+    if (e != hipSuccess) return e;
+  }
+  double* Lc = A.lam_a;
+  double* La = A.lam_b;
+  double* Ln = A.lam_c;
+  e = hipMemcpyAsync(Lc, A.lambda, M * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  const unsigned nbc = blocks_for(N), nbv = blocks_for(M);
+  const double dt = A.dt;
+  for (int n = A.nsteps - 1; n >= 0; --n) {
+    // stage 2 source at y^{n+1}
+    hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, Y(n + 1), Lc, A.rho,
+                       A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF);
+    hipLaunchKernelGGL(k_axpby, dim3(nbv), dim3(ATHREADS), 0, s, M, 0.5, Lc, 0.0, La);
+    hipLaunchKernelGGL(k_axpby, dim3(nbv), dim3(ATHREADS), 0, s, M, 0.5, Lc, 0.0, Ln);
+    e = transport_vjp<ND>(P, H(n), Lc, 0.5 * dt, La, A.fm, A.C, s);
+    if (e != hipSuccess) return e;
+    // stage 1 source at y^{n+1/2}
+    hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, H(n), La, A.rho, A.kP,
+                       A.kF, dt, A.gkP, A.gkF);
+    hipLaunchKernelGGL(k_axpby, dim3(nbv), dim3(ATHREADS), 0, s, M, 1.0, La, 1.0, Ln);
+    e = transport_vjp<ND>(P, Y(n), La, dt, Ln, A.fm, A.C, s);
+    if (e != hipSuccess) return e;
+    double* t = Lc;
+    Lc = Ln;
+    Ln = t;
+  }
+  e = hipMemcpyAsync(A.lambda, Lc, M * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const AdjointArgs& A) {
+  switch (A.P.ndim) {
+    case 1: return adjoint_nd<1>(A);
+    case 2: return adjoint_nd<2>(A);
+    case 3: return adjoint_nd<3>(A);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rhd

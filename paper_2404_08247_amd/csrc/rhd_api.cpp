@@ -13,6 +13,13 @@
 #include "../../include/rhd.h"
 #include "rhd_internal.hpp"
 
+struct Layout_ptrs {
+  double* states;
+  double* lam;
+  double* fm;
+  double* C;
+};
+
 struct rhd_handle {
   rhd_params p;
   rhd::DevParams dp;
@@ -28,8 +35,7 @@ struct rhd_handle {
   double* yhalf;              // nvar * N
   double* partial;            // reduction scratch
   int partial_blocks;
-  double* adj_base;           // adjoint storage (segment states and adjoint scratch)
-  size_t adj_bytes;
+  Layout_ptrs adj;            // adjoint storage (segment states and adjoint scratch)
   // last error
   rhd_status last;
   long long last_cell;
@@ -82,13 +88,14 @@ std::string validate(const rhd_params* p) {
 }
 
 struct Layout {
-  size_t err, yhalf, partial, adj, total;
+  size_t err, yhalf, partial, adj, states, lam, fm, C, total;
 };
 
 Layout layout(const rhd_params* p, int adj_len) {
   const size_t N = (size_t)ncells(p);
   const size_t nv = (size_t)nvar_of(p);
-  Layout L;
+  const size_t nr = (size_t)(1 + p->ndim);
+  Layout L{};
   size_t off = 0;
   L.err = off;
   off = align_up(off + 2 * sizeof(unsigned long long));
@@ -98,10 +105,17 @@ Layout layout(const rhd_params* p, int adj_len) {
   off = align_up(off + (size_t)kPartialBlocks * 4 * sizeof(double));
   L.adj = off;
   if (adj_len > 0) {
-    // y^n and y^{n+1/2} of every step of a segment, plus two adjoint vectors,
-    // plus per-face flux adjoints (3 axes x (1 + ndim) components).
-    off = align_up(off + (size_t)(2 * adj_len + 2) * nv * N * sizeof(double));
-    off = align_up(off + (size_t)3 * (1 + p->ndim) * N * sizeof(double));
+    // y^0..y^k and y^{1/2}..y^{k-1/2} of a segment, three adjoint vectors,
+    // per-face edge-state adjoints (2 (1+ndim) N) and per-cell stencil
+    // contributions (5 (1+ndim) N).
+    L.states = off;
+    off = align_up(off + (size_t)(2 * adj_len + 1) * nv * N * sizeof(double));
+    L.lam = off;
+    off = align_up(off + 3 * nv * N * sizeof(double));
+    L.fm = off;
+    off = align_up(off + 2 * nr * N * sizeof(double));
+    L.C = off;
+    off = align_up(off + 5 * nr * N * sizeof(double));
   }
   L.total = off;
   return L;
@@ -200,8 +214,14 @@ rhd_status rhd_create(const rhd_params* p, const double* rho, const double* kapp
   h->yhalf = reinterpret_cast<double*>(h->ws + L.yhalf);
   h->partial = reinterpret_cast<double*>(h->ws + L.partial);
   h->partial_blocks = kPartialBlocks;
-  h->adj_base = reinterpret_cast<double*>(h->ws + L.adj);
-  h->adj_bytes = L.total - L.adj;
+  if (adjoint_segment_len > 0) {
+    h->adj.states = reinterpret_cast<double*>(h->ws + L.states);
+    h->adj.lam = reinterpret_cast<double*>(h->ws + L.lam);
+    h->adj.fm = reinterpret_cast<double*>(h->ws + L.fm);
+    h->adj.C = reinterpret_cast<double*>(h->ws + L.C);
+  } else {
+    h->adj = Layout_ptrs{nullptr, nullptr, nullptr, nullptr};
+  }
   h->last = RHD_OK;
   h->last_cell = -1;
   *out = h;
@@ -327,8 +347,45 @@ rhd_status rhd_conserved_totals(rhd_handle* h, const double* state, double* out)
 rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int32_t nsteps,
                             double* lambda, double* g_kappa_P, double* g_kappa_F) {
   if (!h) return RHD_EINVAL;
-  (void)state0; (void)dt; (void)nsteps; (void)lambda; (void)g_kappa_P; (void)g_kappa_F;
-  return set_err(h, RHD_EINVAL, -1, "adjoint not available in this build");
+  if (h->adj_len <= 0)
+    return set_err(h, RHD_EINVAL, -1, "handle created without adjoint workspace (adjoint_segment_len = 0)");
+  if (nsteps < 1 || nsteps > h->adj_len)
+    return set_err(h, RHD_EINVAL, -1, "nsteps must be in 1..adjoint_segment_len");
+  if (!state0 || !lambda || !g_kappa_P || misaligned(state0) || misaligned(lambda) ||
+      misaligned(g_kappa_P) || misaligned(g_kappa_F) || !std::isfinite(dt) || !(dt > 0.0))
+    return set_err(h, RHD_EINVAL, -1, "invalid state0, lambda, g_kappa_P, g_kappa_F or dt");
+  if (state0 == lambda) return set_err(h, RHD_EINVAL, -1, "state0 and lambda must not alias");
+  if (!h->dp.kF_alias && !g_kappa_F)
+    return set_err(h, RHD_EINVAL, -1, "a separate kappa_F needs g_kappa_F");
+  for (int d = 0; d < h->p.ndim; ++d)
+    if (h->p.bc[d] != RHD_BC_PERIODIC)
+      return set_err(h, RHD_EINVAL, -1, "the adjoint supports periodic axes only");
+  hipError_t e = rhd::launch_reset_err(h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset");
+  const size_t M = (size_t)nvar_of(&h->p) * (size_t)h->dp.N;
+  rhd::AdjointArgs A;
+  A.P = h->dp;
+  A.mixed = (h->p.precision == RHD_MIXED);
+  A.state0 = state0;
+  A.dt = dt;
+  A.nsteps = nsteps;
+  A.lambda = lambda;
+  A.gkP = g_kappa_P;
+  A.gkF = g_kappa_F;
+  A.rho = h->rho;
+  A.kP = h->kP;
+  A.kF = h->kF;
+  A.states = h->adj.states;
+  A.lam_a = h->adj.lam;
+  A.lam_b = h->adj.lam + M;
+  A.lam_c = h->adj.lam + 2 * M;
+  A.fm = h->adj.fm;
+  A.C = h->adj.C;
+  A.err = h->err;
+  A.stream = h->stream;
+  e = rhd::launch_adjoint(A);
+  if (e != hipSuccess) return hip_fail(h, e, "adjoint launch");
+  return finish(h);
 }
 
 rhd_status rhd_last_error(const rhd_handle* h, int64_t* cell, char* msg, size_t len) {

@@ -43,4 +43,29 @@ hipError_t launch_reset_err(unsigned long long* err, hipStream_t s);
 hipError_t launch_totals(const DevParams& P, const double* y, double* partial, int nblocks,
                          hipStream_t s);
 
+// Arguments of one adjoint segment (rhd_adjoint.hip).
+struct AdjointArgs {
+  DevParams P;
+  bool mixed;
+  const double* state0;   // segment start (caller)
+  double dt;
+  int nsteps;
+  double* lambda;         // caller's adjoint vector (in: end, out: start)
+  double* gkP;
+  double* gkF;            // may be null
+  const double* rho;
+  const double* kP;
+  const double* kF;
+  double* states;         // (2 nsteps + 1) states: y^0..y^k, then y^{1/2}..y^{k-1/2}
+  double* lam_a;
+  double* lam_b;
+  double* lam_c;
+  double* fm;             // 2 (1 + ndim) N
+  double* C;              // 5 (1 + ndim) N
+  unsigned long long* err;
+  hipStream_t stream;
+};
+
+hipError_t launch_adjoint(const AdjointArgs& A);
+
 }  // namespace rhd

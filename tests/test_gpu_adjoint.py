@@ -1,0 +1,160 @@
+"""GPU adjoint (reverse mode through the C ABI) against the oracle's forward-mode
+dual numbers and against finite differences.
+
+Dot-product test: for random directions (dy0, dkappa) and a random lambda,
+<lambda, J (dy0, dkappa)> from the oracle's dual-number tangent must equal
+<adjoint(lambda), (dy0, dkappa)> from rhd_step_adjoint. States are made free of
+exact ties (where the PPM limiter has a kink) by a smooth 1 % modulation.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_08247_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+def _to(torch_dev, a):
+    torch, dev = torch_dev
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+def _tie_free(y0):
+    y = y0.copy()
+    nz, ny, nx = y.shape[1:]
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    y[0] *= 1.0 + 0.01 * np.sin(0.7 * X + 0.3 * Y + 0.2 * Z + 0.1)
+    return y
+
+
+CASES = {
+    "c4_2d": lambda: W.config4(n=(20, 16), nsteps=3),
+    "c3_3d_fp64": lambda: W.config3(n=(12, 10, 8), nsteps=2, precision="fp64"),
+    "c5_3d_fp64": lambda: W.config5(n=(12, 10, 8), nsteps=2, precision="fp64"),
+    "c2_3d": lambda: W.config2(n=(12, 10, 8), nsteps=2),
+    "c5_3d_order1": lambda: W.config5(n=(10, 8, 8), nsteps=2, precision="fp64", v_order=1),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_adjoint_dot_product_matches_oracle_dual(torch_dev, orc, case):
+    torch, dev = torch_dev
+    from paper_2404_08247_amd import rhd
+    w = CASES[case]()
+    _say("adjoint dot product", case, w.n, w.nsteps)
+    p = w.params
+    y0 = _tie_free(w.y0)
+    rng = np.random.default_rng(17)
+    sh = y0[0].shape
+    nd = w.ndim
+    dy = np.zeros_like(y0)
+    dy[0] = y0[0] * rng.uniform(-1, 1, sh)
+    dy[1 + nd] = y0[1 + nd] * rng.uniform(-1, 1, sh) * 1e-2
+    for d in range(nd):
+        dy[1 + d] = 1e-3 * p["c"] * y0[0] * rng.uniform(-1, 1, sh)
+        dy[2 + nd + d] = 1e-3 * rng.uniform(-1, 1, sh)
+    dk = w.kappa_P * rng.uniform(-1, 1, sh)
+    yN, t, st, _ = orc.step_dual(p, y0, dy, w.rho, w.kappa_P, dk, None, None, w.dt, w.nsteps)
+    assert st == 0
+    lam = np.zeros_like(yN)
+    for v in range(w.nvar):
+        lam[v] = rng.normal(size=sh) / max(np.abs(yN[v]).max(), 1e-300)
+    lhs = float((lam * t).sum())
+
+    S = rhd.Solver(p, _to(torch_dev, w.rho), _to(torch_dev, w.kappa_P), None, w.nsteps, dev)
+    lam_d = _to(torch_dev, lam)
+    gk = torch.zeros_like(S.kappa_P)
+    S.step_adjoint(_to(torch_dev, y0), w.dt, w.nsteps, lam_d, gk, None)
+    lam0 = lam_d.cpu().numpy()
+    g = gk.cpu().numpy()
+    rhs = float((lam0 * dy).sum() + (g * dk).sum())
+    terms = np.abs(lam0 * dy).sum() + np.abs(g * dk).sum()
+    _say("  <lam, J d> =", lhs, " <J^T lam, d> =", rhs, " rel", abs(lhs - rhs) / abs(lhs))
+    assert abs(lhs - rhs) <= 1e-9 * terms, (lhs, rhs, terms)
+
+
+def test_checkpoint_interval_does_not_change_gradients(torch_dev):
+    torch, dev = torch_dev
+    from paper_2404_08247_amd import autograd as AG, rhd
+    w = W.config4(n=(24, 20), nsteps=6)
+    p = w.params
+    rho = _to(torch_dev, w.rho)
+    nd = w.ndim
+    cv = p["kB_over_mu"] / (p["gamma"] - 1)
+    ke = (w.y0[2 + nd:] ** 2).sum(axis=0) / (2 * w.rho)
+    T0 = _to(torch_dev, (w.y0[1 + nd] - ke) / (w.rho * cv))
+    mom = _to(torch_dev, w.y0[2 + nd:])
+    mask = _to(torch_dev, w.objective_mask.astype(np.float64))
+    out = []
+    for k in (2, 3, 6):
+        kap = _to(torch_dev, w.kappa_P)
+        S = rhd.Solver(p, rho, kap, None, k, dev)
+        J, gk, gT = AG.patch_energy_gradients(p, T0, mom, rho, kap, mask, w.dt, w.nsteps, k, S)
+        out.append((J.item(), gk.cpu().numpy(), gT.cpu().numpy()))
+    for J, gk, gT in out[1:]:
+        assert J == out[0][0]
+        np.testing.assert_allclose(gk, out[0][1], rtol=1e-12, atol=1e-12 * np.abs(out[0][1]).max())
+        np.testing.assert_allclose(gT, out[0][2], rtol=1e-12, atol=1e-12 * np.abs(out[0][2]).max())
+
+
+def test_patch_energy_gradient_matches_finite_differences(torch_dev, orc):
+    torch, dev = torch_dev
+    from paper_2404_08247_amd import autograd as AG, rhd
+    # smooth, tie-free 2-D problem (periodic), J = sum of E over the central patch
+    w = W.config4(n=(24, 20), nsteps=4)
+    p = w.params
+    nd = w.ndim
+    ny, nx = 20, 24
+    Y, X = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    T = (1.0 + 0.5 * np.exp(-((X - 11.3) ** 2 + (Y - 9.7) ** 2) / 18.0)) * \
+        (1.0 + 0.02 * np.sin(0.5 * X + 0.3 * Y + 0.2))
+    T = T.reshape(1, ny, nx)
+    mom = w.y0[2 + nd:].copy()
+    rho = _to(torch_dev, w.rho)
+    kap = _to(torch_dev, w.kappa_P)
+    mask = w.objective_mask.astype(np.float64)
+    S = rhd.Solver(p, rho, kap, None, 2, dev)
+    J, gk, gT = AG.patch_energy_gradients(p, _to(torch_dev, T), _to(torch_dev, mom), rho, kap,
+                                          _to(torch_dev, mask), w.dt, w.nsteps, 2, S)
+    gk = gk.cpu().numpy()
+    gT = gT.cpu().numpy()
+    cv = p["kB_over_mu"] / (p["gamma"] - 1)
+
+    def J_of(Tf, kf):
+        y = np.zeros((2 + 2 * nd, 1, ny, nx))
+        y[0] = p["a_r"] * Tf ** 4
+        y[1 + nd] = w.rho * cv * Tf + (mom ** 2).sum(axis=0) / (2 * w.rho)
+        y[2 + nd:] = mom
+        yo, st, _ = orc.step(p, y, w.rho, kf, None, w.dt, w.nsteps)
+        assert st == 0
+        return (yo[0] * mask).sum()
+
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        j, i = int(rng.integers(0, ny)), int(rng.integers(0, nx))
+        hk = 1e-5 * w.kappa_P[0, j, i]
+        kp, km = w.kappa_P.copy(), w.kappa_P.copy()
+        kp[0, j, i] += hk
+        km[0, j, i] -= hk
+        fd = (J_of(T, kp) - J_of(T, km)) / (2 * hk)
+        assert abs(fd - gk[0, j, i]) <= 1e-5 * abs(gk).max(), (fd, gk[0, j, i])
+        hT = 1e-6 * T[0, j, i]
+        Tp, Tm = T.copy(), T.copy()
+        Tp[0, j, i] += hT
+        Tm[0, j, i] -= hT
+        fdT = (J_of(Tp, w.kappa_P) - J_of(Tm, w.kappa_P)) / (2 * hT)
+        assert abs(fdT - gT[0, j, i]) <= 1e-5 * abs(gT).max(), (fdT, gT[0, j, i])
