@@ -35,15 +35,86 @@ def stage_bytes_per_cell(ndim):
     return 8 * (nvar + 2 + nvar), 8 * (2 * nvar + 2 + nvar)
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def bench_mixed(torch, rhd, W, dev, to):
+    """3-D 256^3 dynamic-diffusion workload (v = 0.01c, slabs of tau_cell 0.1/10/1000,
+    chat = c/50, 300 steps): FP64 and mixed precision on the same inputs, and the
+    mixed result's L-inf error relative to FP64 per field."""
+    out = {"workload": "3-D 256^3 dynamic diffusion, periodic, chat = c/50, 300 steps"}
+    res = {}
+    for prec in ("fp64", "mixed"):
+        w = W.config3(precision=prec)
+        y = to(w.y0)
+        S = rhd.Solver(w.params, to(w.rho), to(w.kappa_P), None, 0, dev)
+        S.step(y, w.dt, 2)
+        y = to(w.y0)
+        dt_s = _timed(torch, lambda: S.step(y, w.dt, w.nsteps))
+        res[prec] = (y, dt_s)
+        out[prec] = {"value": w.ncells * w.nsteps / dt_s, "unit": "cell-updates/s",
+                     "ms_per_step": dt_s / w.nsteps * 1e3}
+        print(f"[bench] c3 {prec}: {dt_s / w.nsteps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    a, b = res["mixed"][0], res["fp64"][0]
+    errs = [float(((a[v] - b[v]).abs().max() / b[v].abs().max()).item()) for v in range(a.shape[0])]
+    out["speedup"] = res["fp64"][1] / res["mixed"][1]
+    out["max_rel_err_vs_fp64_per_field"] = errs
+    return out
+
+
+def bench_adjoint(torch, rhd, W, dev, to):
+    """2-D 512^2 adjoint workload (200 steps, checkpoints every 20): forward with
+    checkpoint copies, then the full backward (recompute + reverse of every
+    segment), J = sum of E over the central 64^2 patch."""
+    from paper_2404_08247_amd import autograd as AG
+    w = W.config4()
+    p = w.params
+    nd = w.ndim
+    cv = p["kB_over_mu"] / (p["gamma"] - 1)
+    ke = (w.y0[2 + nd:] ** 2).sum(axis=0) / (2 * w.rho)
+    T0 = to((w.y0[1 + nd] - ke) / (w.rho * cv))
+    rho, kap = to(w.rho), to(w.kappa_P)
+    mom, mask = to(w.y0[2 + nd:]), to(w.objective_mask.astype(np.float64))
+    S = rhd.Solver(p, rho, kap, None, w.ckpt_every, dev)
+    kap.requires_grad_(True)
+    T = T0.clone().requires_grad_(True)
+    F = torch.zeros((nd,) + tuple(T0.shape), dtype=T0.dtype, device=dev)
+    AG.patch_energy_gradients(p, T0, mom, rho, kap, mask, w.dt, 4, 2, S)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y0 = AG.initial_state(T, T, F, mom, rho, p)
+    yN = AG.RHDFunction.apply(y0, kap, S, w.dt, w.nsteps, w.ckpt_every)
+    J = (yN[0] * mask).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gT, gk = torch.autograd.grad(J, [T, kap])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    print(f"[bench] c4 adjoint: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms",
+          file=sys.stderr, flush=True)
+    return {"workload": "2-D 512^2, periodic, chat = c, 200 steps, checkpoints every 20",
+            "forward_s": fwd, "backward_s": bwd, "adjoint_forward_ratio": bwd / fwd,
+            "forward_cell_updates_per_s": w.ncells * w.nsteps / fwd,
+            "J": float(J.item()), "grad_norm_kappa": float(gk.norm().item()),
+            "grad_norm_T0": float(gT.norm().item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--cpu-steps", type=int, default=8,
+    ap.add_argument("--cpu-steps", type=int, default=60,
                     help="oracle steps in the CPU-baseline sample (0 = skip)")
-    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision line item")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision and adjoint line items")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-mebibyte buffer once (a plain copy "
                          "kernel of known size, to scale the HBM byte counters)")
@@ -97,19 +168,9 @@ def main():
           f"{wall / args.steps * 1e6:.1f} us", file=sys.stderr, flush=True)
 
     extras = {}
-    if not args.no_extras and args.precision == "fp64":
-        wm = W.config2(precision="mixed")
-        ym = to(wm.y0)
-        Sm = rhd.Solver(wm.params, rho, kap, None, 0, dev)
-        Sm.step(ym, wm.dt, max(1, args.warmup))
-        torch.cuda.synchronize()
-        tm = time.perf_counter()
-        Sm.step(ym, wm.dt, args.steps)
-        torch.cuda.synchronize()
-        wallm = time.perf_counter() - tm
-        extras["mixed_precision"] = {"value": cells * args.steps / wallm,
-                                     "unit": "cell-updates/s", "steps": args.steps,
-                                     "ms_per_step": wallm / args.steps * 1e3}
+    if not args.no_extras:
+        extras["mixed_vs_fp64"] = bench_mixed(torch, rhd, W, dev, to)
+        extras["adjoint"] = bench_adjoint(torch, rhd, W, dev, to)
 
     cpu = None
     if args.cpu_steps > 0:
@@ -124,7 +185,7 @@ def main():
                          f"workload (OpenMP over cells), {tcpu:.1f} s"}
 
     line = {
-        "metric": "IMEX RHD cell-updates/s (FP64 step; mixed precision reported alongside)",
+        "metric": "IMEX RHD cell-updates/s, FP64 vs mixed; adjoint/forward time ratio",
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
