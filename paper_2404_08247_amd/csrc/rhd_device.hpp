@@ -40,22 +40,21 @@ __device__ __forceinline__ T mc_slope(T dl, T dr) {   // dl = a0 - a(-1), dr = a
   return (dl * dr > T(0)) ? copysign(lim, dc) : T(0);
 }
 
-// monotonised edge offsets (l, r) of a cell from its raw interface offsets
+// monotonised edge offsets (l, r) of a cell from its raw interface offsets;
+// branch-free (selects), so the variables of a cell interleave
 template <typename T>
 __device__ __forceinline__ void ppm_monotone(T& l, T& r) {
-  if (r * l >= T(0)) {          // (r - 0)(0 - l) <= 0: local extremum
-    l = T(0);
-    r = T(0);
-  } else {
-    const T del = r - l;
-    const T a6 = T(-3) * (l + r);
-    const T del2 = del * del;
-    if (del * a6 > del2) {
-      l = T(-2) * r;
-    } else if (del * a6 < -del2) {
-      r = T(-2) * l;
-    }
-  }
+  const T del = r - l;
+  const T a6 = T(-3) * (l + r);
+  const T del2 = del * del;
+  const T da6 = del * a6;
+  const bool ext = (r * l >= T(0));       // (r - 0)(0 - l) <= 0: local extremum
+  const bool cl = da6 > del2;
+  const bool cr = da6 < -del2;
+  const T nl = cl ? T(-2) * r : l;
+  const T nr = (!cl && cr) ? T(-2) * l : r;
+  l = ext ? T(0) : nl;
+  r = ext ? T(0) : nr;
 }
 
 // edge states of the middle cell of a[0..4] (double values in, double out)

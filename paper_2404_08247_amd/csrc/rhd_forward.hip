@@ -24,11 +24,28 @@ namespace rhd {
 
 constexpr int HALO = 3;
 constexpr int NTHREADS = 256;
+// Minimum waves per SIMD the stage kernels are compiled for (caps VGPRs at
+// 512 / RHD_STAGE_WAVES; excess live values go to AGPRs).
+#ifndef RHD_STAGE_WAVES
+#define RHD_STAGE_WAVES 1
+#endif
 
+#ifndef RHD_TX
+#define RHD_TX 32
+#endif
+#ifndef RHD_ZCHUNK
+#define RHD_ZCHUNK 16
+#endif
+#ifndef RHD_MIN_BLOCKS
+#define RHD_MIN_BLOCKS 2048
+#endif
+#ifndef RHD_XCD_REMAP
+#define RHD_XCD_REMAP 1
+#endif
 template <int ND> struct TileShape;
 template <> struct TileShape<1> { static constexpr int TX = 256, TY = 1; };
-template <> struct TileShape<2> { static constexpr int TX = 32, TY = 8; };
-template <> struct TileShape<3> { static constexpr int TX = 32, TY = 8; };
+template <> struct TileShape<2> { static constexpr int TX = RHD_TX, TY = 256 / RHD_TX; };
+template <> struct TileShape<3> { static constexpr int TX = RHD_TX, TY = 256 / RHD_TX; };
 
 // Ghost rule along one axis: returns the source cell of (possibly outside)
 // coordinate g and whether the normal flux component flips sign. Positions
@@ -56,7 +73,7 @@ __device__ __forceinline__ void report(unsigned long long* err, long long cell, 
 }
 
 template <int ND, int MODE, typename TT>
-__global__ void __launch_bounds__(NTHREADS)
+__global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(RHD_STAGE_WAVES)))
 k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw,
         const double* __restrict__ rho, const double* __restrict__ kP,
         const double* __restrict__ kF, double dt, int zchunk, unsigned long long* err) {
@@ -83,9 +100,25 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   const int tx = tid % TX;
   const int ty = tid / TX;
   const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
-  const int x0 = blockIdx.x * TX;
-  const int y0 = blockIdx.y * TY;
-  const int z0 = blockIdx.z * zchunk;
+  // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+  // Renumber them so that each XCD gets a contiguous run of tiles (x fastest,
+  // then y, then z) and the halo planes/rows that neighbouring tiles share are
+  // read through the same L2.
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  {
+    const int gxn = gridDim.x, gyn = gridDim.y;
+    const int nb = gxn * gyn * gridDim.z;
+    if (RHD_XCD_REMAP && (nb % 8) == 0) {
+      const int lin = (blockIdx.z * gyn + blockIdx.y) * gxn + blockIdx.x;
+      const int log_id = (lin % 8) * (nb / 8) + lin / 8;
+      bx = log_id % gxn;
+      by = (log_id / gxn) % gyn;
+      bz = log_id / (gxn * gyn);
+    }
+  }
+  const int x0 = bx * TX;
+  const int y0 = by * TY;
+  const int z0 = bz * zchunk;
   const int z1 = min(z0 + zchunk, nz);
   const int gx = x0 + tx, gy = y0 + ty;
   const bool valid = (gx < nx) && (gy < ny);
@@ -147,7 +180,51 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, Um, Up, zfl_prev);
   }
 
+  // halo position of this thread and its source cell within a plane
+  constexpr int NHX = 2 * HALO * TY;
+  constexpr int NHY = (ND >= 2) ? 2 * HALO * TX : 0;
+  static_assert(NHX + NHY <= NTHREADS, "one halo position per thread");
+  const long long plane = (long long)nx * ny;
+  long long hoff = -1;
+  int htile = 0;
+  bool hfx = false, hfy = false;
+  if (tid < NHX + NHY) {
+    int lx, ly;
+    if (tid < NHX) {
+      const int row = tid / (2 * HALO), j = tid % (2 * HALO);
+      lx = (j < HALO) ? j : TX + j;
+      ly = row + (ND >= 2 ? HALO : 0);
+    } else {
+      const int h2 = tid - NHX;
+      const int col = h2 % TX, j = h2 / TX;
+      lx = col + HALO;
+      ly = (j < HALO) ? j : TY + j;
+    }
+    const int sx = ghost(x0 + lx - HALO, nx, P.bc[0], hfx);
+    const int sy = (ND >= 2) ? ghost(y0 + ly - HALO, ny, P.bc[1], hfy) : 0;
+    hoff = (long long)sy * nx + sx;
+    htile = ly * TW + lx;
+  }
+
   for (int k = z0; k < z1; ++k) {
+    // ---- source-phase inputs of the own cell, issued before the transport so
+    // their latency overlaps it: E_gas and rho v of the stencil state, and for
+    // stage 2 the whole own-cell y^n; rho and kappa.
+    constexpr int NPRE = (MODE == MODE_STAGE2) ? (1 + ND) + (2 + 2 * ND) : (1 + ND);
+    double pre[NPRE];
+    double pre_rho = 1.0, pre_kp = 0.0, pre_kf = 0.0;
+    if constexpr (MODE != MODE_TRANSPORT) {
+      const long long qc = cidx(P, cx, cy, k);   // in range for every thread
+#pragma unroll
+      for (int m = 0; m <= ND; ++m) pre[m] = ys[(1 + ND + m) * N + qc];
+      if constexpr (MODE == MODE_STAGE2) {
+#pragma unroll
+        for (int m = 0; m < 2 + 2 * ND; ++m) pre[1 + ND + m] = yo[m * N + qc];
+      }
+      pre_rho = rho[qc];
+      pre_kp = kP[qc];
+      pre_kf = P.kF_alias ? pre_kp : kF[qc];
+    }
     // ---------------- stage the plane's (E, F) tile in LDS ----------------
     double own[NR];
     if constexpr (ND == 3) {
@@ -164,79 +241,72 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       for (int r = 0; r < NR; ++r)
         s_area[r][t] = ((own_fx && r == 1) || (own_fy && r == 2)) ? -own[r] : own[r];
     }
-    // halo: 3 columns left and right of every row; 3 rows above and below
-    constexpr int NHX = 2 * HALO * TY;
-    constexpr int NHY = (ND >= 2) ? 2 * HALO * TX : 0;
-    for (int h = tid; h < NHX + NHY; h += NTHREADS) {
-      int lx, ly;
-      if (h < NHX) {
-        const int row = h / (2 * HALO), j = h % (2 * HALO);
-        lx = (j < HALO) ? j : TX + j;       // tile column
-        ly = row + (ND >= 2 ? HALO : 0);
-      } else {
-        const int h2 = h - NHX;
-        const int col = h2 % TX, j = h2 / TX;
-        lx = col + HALO;
-        ly = (j < HALO) ? j : TY + j;
-      }
-      bool fx, fy = false;
-      const int sx = ghost(x0 + lx - HALO, nx, P.bc[0], fx);
-      const int sy = (ND >= 2) ? ghost(y0 + ly - HALO, ny, P.bc[1], fy) : 0;
-      const long long q = cidx(P, sx, sy, k);
+    // halo (3 columns left/right of every row, 3 rows above/below): each thread
+    // copies at most one position, whose source offset was resolved once per
+    // block (hoff < 0: no position)
+    if (hoff >= 0) {
+      const long long q = (long long)k * plane + hoff;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         double val = ys[r * N + q];
-        if ((fx && r == 1) || (fy && r == 2)) val = -val;
-        s_area[r][ly * TW + lx] = val;
+        if ((hfx && r == 1) || (hfy && r == 2)) val = -val;
+        s_area[r][htile] = val;
       }
     }
     __syncthreads();
 
     // ---------------- PPM edge states, once per cell ----------------
+    // y items first: their count TX (TY + 2) is a multiple of 64 for the 2-D/3-D
+    // tiles, so no wave mixes x and y items
     for (int e = tid; e < NEX + NEY; e += NTHREADS) {
-      if (e < NEX) {
-        const int row = e / (TX + 2), col = e % (TX + 2);    // cell x0 + col - 1
-        const int base = (row + (ND >= 2 ? HALO : 0)) * TW + col;  // = centre - 2
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const double* a = &s_area[r][base];
-          double l, rr;
-          ppm_edges5<TT>(a[0], a[1], a[2], a[3], a[4], l, rr);
-          s_exL[r][e] = l;
-          s_exR[r][e] = rr;
-        }
-      } else if constexpr (ND >= 2) {
-        const int e2 = e - NEX;
-        const int col = e2 % TX, row = e2 / TX;              // cell y0 + row - 1
+      if (ND >= 2 && e < NEY) {
+        const int col = e % TX, row = e / TX;                // cell y0 + row - 1
         const int base = row * TW + col + HALO;              // = centre - 2 rows
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const double* a = &s_area[r][base];
           double l, rr;
           ppm_edges5<TT>(a[0], a[TW], a[2 * TW], a[3 * TW], a[4 * TW], l, rr);
-          s_eyL[r][e2] = l;
-          s_eyR[r][e2] = rr;
+          s_eyL[r][e] = l;
+          s_eyR[r][e] = rr;
+        }
+      } else {
+        const int ex = e - NEY;
+        const int row = ex / (TX + 2), col = ex % (TX + 2);  // cell x0 + col - 1
+        const int base = (row + (ND >= 2 ? HALO : 0)) * TW + col;  // = centre - 2
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double* a = &s_area[r][base];
+          double l, rr;
+          ppm_edges5<TT>(a[0], a[1], a[2], a[3], a[4], l, rr);
+          s_exL[r][ex] = l;
+          s_exR[r][ex] = rr;
         }
       }
     }
     __syncthreads();
 
     // ---------------- HLL fluxes, once per face (into the tile's LDS) -------
-    for (int f = tid; f < NFX + NFY; f += NTHREADS) {
+    // x faces occupy items [0, NFXP) (padded to a multiple of 64 so no wave
+    // mixes x and y faces), y faces follow
+    constexpr int NFXP = (ND >= 2) ? ((NFX + 63) / 64) * 64 : NFX;
+    for (int f = tid; f < NFXP + NFY; f += NTHREADS) {
       double Um[NR], Up[NR], fl[NR];
-      if (f < NFX) {
-        const int row = f / (TX + 1), fx = f % (TX + 1);     // between cells fx-1 | fx
-        const int eb = row * (TX + 2) + fx;
+      if (f < NFXP) {
+        if (f < NFX) {
+          const int row = f / (TX + 1), fx = f % (TX + 1);   // between cells fx-1 | fx
+          const int eb = row * (TX + 2) + fx;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          Um[r] = s_exR[r][eb];
-          Up[r] = s_exL[r][eb + 1];
+          for (int r = 0; r < NR; ++r) {
+            Um[r] = s_exR[r][eb];
+            Up[r] = s_exL[r][eb + 1];
+          }
+          hll_flux<ND, 0, TT>(clo, c, ch, chc, cch, Um, Up, fl);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) s_area[r][f] = fl[r];
         }
-        hll_flux<ND, 0, TT>(clo, c, ch, chc, cch, Um, Up, fl);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) s_area[r][f] = fl[r];
       } else if constexpr (ND >= 2) {
-        const int f2 = f - NFX;
+        const int f2 = f - NFXP;
         const int col = f2 % TX, fy = f2 / TX;               // between rows fy-1 | fy
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -313,28 +383,25 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       double E, F[ND], Eg, Pm[ND];
       double tau;
       if constexpr (MODE == MODE_STAGE1) {
-        E = ys[q] + dt * s[0];
+        E = own[0] + dt * s[0];
 #pragma unroll
-        for (int k2 = 0; k2 < ND; ++k2) F[k2] = ys[(1 + k2) * N + q] + dt * s[1 + k2];
-        Eg = ys[(1 + ND) * N + q];
+        for (int k2 = 0; k2 < ND; ++k2) F[k2] = own[1 + k2] + dt * s[1 + k2];
+        Eg = pre[0];
 #pragma unroll
-        for (int k2 = 0; k2 < ND; ++k2) Pm[k2] = ys[(2 + ND + k2) * N + q];
+        for (int k2 = 0; k2 < ND; ++k2) Pm[k2] = pre[1 + k2];
         tau = dt;
       } else {
         const double hdt = 0.5 * dt;
-        E = 0.5 * (yo[q] + ys[q]) + hdt * s[0];
+        E = 0.5 * (pre[1 + ND] + own[0]) + hdt * s[0];
 #pragma unroll
         for (int k2 = 0; k2 < ND; ++k2)
-          F[k2] = 0.5 * (yo[(1 + k2) * N + q] + ys[(1 + k2) * N + q]) + hdt * s[1 + k2];
-        Eg = 0.5 * (yo[(1 + ND) * N + q] + ys[(1 + ND) * N + q]);
+          F[k2] = 0.5 * (pre[2 + ND + k2] + own[1 + k2]) + hdt * s[1 + k2];
+        Eg = 0.5 * (pre[2 + 2 * ND] + pre[0]);
 #pragma unroll
-        for (int k2 = 0; k2 < ND; ++k2)
-          Pm[k2] = 0.5 * (yo[(2 + ND + k2) * N + q] + ys[(2 + ND + k2) * N + q]);
+        for (int k2 = 0; k2 < ND; ++k2) Pm[k2] = 0.5 * (pre[3 + 2 * ND + k2] + pre[1 + k2]);
         tau = hdt;
       }
-      const double kp = kP[q];
-      const double kf = P.kF_alias ? kp : kF[q];
-      const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, kf, tau);
+      const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, tau);
       if (st) report(err, q, st);
       yw[q] = E;
 #pragma unroll
@@ -425,8 +492,8 @@ static hipError_t launch_nd(const DevParams& P, const double* ys, const double* 
   if (ND == 3) {
     // enough workgroups to fill 256 CUs several times, chunks of >= 8 planes
     const long long cols = (long long)gxn * gyn;
-    zchunk = 16;
-    while (zchunk > 8 && cols * ((nz + zchunk - 1) / zchunk) < 2048) zchunk /= 2;
+    zchunk = RHD_ZCHUNK;
+    while (zchunk > 4 && cols * ((nz + zchunk - 1) / zchunk) < RHD_MIN_BLOCKS) zchunk /= 2;
     if (zchunk > nz) zchunk = nz;
   }
   const int gzn = (nz + zchunk - 1) / zchunk;
