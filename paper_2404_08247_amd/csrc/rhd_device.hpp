@@ -143,14 +143,13 @@ __device__ __forceinline__ void hll_flux(int closure, double c, double chat, dou
 // conservation; repeat with the new v and F until the v- and F-dependent part
 // of R changes by <= outer_rtol (relatively, or relative to R).
 // ---------------------------------------------------------------------------
-template <int ND>
-__device__ __forceinline__ void closure_full(int closure, double c, double E, const double* F,
-                                             double (*D)[ND]) {
-  double g = 0.0, iso = 1.0 / 3.0;
+// (iso, g) of the closure tensor D = iso I + g F F^T (M1: iso = 1/3 - f^2 h,
+// g = 3 h / max(|F|^2, (cE)^2); Eddington: iso = 1/3, g = 0)
+__device__ __forceinline__ void closure_ig(int closure, double c, double E, double F2, double& iso,
+                                           double& g) {
+  iso = 1.0 / 3.0;
+  g = 0.0;
   if (closure != 1) {
-    double F2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < ND; ++k) F2 += F[k] * F[k];
     const double cE = c * E;
     const double r = rcp(fmax(F2, cE * cE));
     const double f2 = F2 * r;
@@ -158,10 +157,6 @@ __device__ __forceinline__ void closure_full(int closure, double c, double E, co
     g = 3.0 * h * r;
     iso -= f2 * h;
   }
-#pragma unroll
-  for (int j = 0; j < ND; ++j)
-#pragma unroll
-    for (int k = 0; k < ND; ++k) D[j][k] = g * F[j] * F[k] + ((j == k) ? iso : 0.0);
 }
 
 template <int ND>
@@ -171,15 +166,19 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   const double chiE = chiP;
   const double chiF = rho * kF;
   if (chiP == 0.0 && chiF == 0.0) return 0u;
-  const double c = P.c, ch = P.chat;
+  const double ch = P.chat;
   const double k_cc = P.c_over_chat;
   const double Cv = rho * P.cv_mass;
   const double inv_Cv = rcp(Cv);
   const double inv_rho = rcp(rho);
   const double inv_tch = rcp(tau * ch);
   const double ar = P.a_r;
+  const bool o2 = (P.v_order == 2);
 
+  // inputs y(t) (kept for every outer pass): E, E_gas, F, rho v
   const double E0 = E, Eg0 = Eg;
+  // lagged v and F of the current pass (start: y(t)); F and momentum carry the
+  // latest iterate, the input F(t) and (rho v)(t) are kept in F0 / P0
   double F0[ND], P0[ND], v[ND], Fb[ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
@@ -192,46 +191,31 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   double Egas = Eg0;
   double R = 0.0;
   const double tol = P.newton_rtol * (Eg0 + k_cc * E0);
-  // dF_R/dR of the simplified Jacobian; fixed for the call
+  // simplified Jacobian (fixed for the call): dF_R/dR and the T^3 factor of dF_R/dE_gas
   const double J22 = -rcp(ch * chiE * tau) - 1.0;
   const double J21c = 4.0 * chiP * ar * rcp(chiE * Cv);
   const double ctau = ch * tau;
-
-  double Enew = E0, Fnew[ND], Pnew[ND];
-#pragma unroll
-  for (int k = 0; k < ND; ++k) {
-    Fnew[k] = F0[k];
-    Pnew[k] = P0[k];
-  }
+  double Enew = E0;
   unsigned status = 0u;
 
   for (int ko = 0; ko < P.outer_maxit; ++ko) {
-    double v2 = 0.0, vF = 0.0;
+    double v2 = 0.0, vF = 0.0, F2 = 0.0;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
       v2 += v[k] * v[k];
       vF += v[k] * Fb[k];
+      F2 += Fb[k] * Fb[k];
     }
     const double KE = 0.5 * rho * v2;
     const double b2 = v2 * P.inv_c2;
-    double D[ND][ND];
-    closure_full<ND>(P.closure, c, Eb, Fb, D);
-    double Dv[ND];
-    double vDv = 0.0;
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < ND; ++k) s += D[j][k] * v[k];
-      Dv[j] = s;
-      vDv += v[j] * s;
-    }
-    const bool o2 = (P.v_order == 2);
-    const double Afac = o2 ? 1.0 + 0.5 * b2 : 1.0;
+    double iso, g;
+    closure_ig(P.closure, P.c, Eb, F2, iso, g);   // D frozen for this pass
+    const double vDv = iso * v2 + g * vF * vF;
+    // R/(tau chat) = A(T) - B E + C  =>  E(E_gas, R) = (A(T) + C - R/(tau chat)) / B
     const double B = o2 ? chiE * (1.0 + 0.5 * b2) - (chiF - chiE) * (b2 + vDv * P.inv_c2) : chiE;
     const double inv_B = rcp(B);
     const double Cc = (2.0 * chiE - chiF) * vF * P.inv_c2;
-    const double Aco = chiP * ar * Afac;
+    const double Aco = chiP * ar * (o2 ? 1.0 + 0.5 * b2 : 1.0);
 
     // ---- inner Newton on (E_gas, R) ----
     bool conv = false;
@@ -256,40 +240,35 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       break;
     }
 
-    // ---- energy from conservation; flux and momentum ----
+    // ---- energy from conservation; flux (eq. numF1 / numF2) and momentum ----
     Enew = E0 - P.chat_over_c * (Egas - Eg0);
     const double Tn = (Egas - KE) * inv_Cv;
     const double Tn2 = Tn * Tn;
     const double Bn = ar * Tn2 * Tn2;
     const double inv_den = rcp(o2 ? 1.0 + ctau * chiF * (1.0 + 0.5 * b2) : 1.0 + ctau * chiF);
     const double xv = chiP * Bn + (o2 ? 0.0 : (chiF - chiE) * Enew);
-    double vnew[ND];
-    double v2n = 0.0;
+    const double gvF = g * vF;
+    double v2n = 0.0, wF_new = 0.0, Fv_new = 0.0;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
-      Fnew[k] = (F0[k] + ctau * (xv * v[k] + chiF * Enew * Dv[k])) * inv_den;
-      Pnew[k] = P0[k] - (Fnew[k] - F0[k]) * P.inv_c_chat;
-      vnew[k] = Pnew[k] * inv_rho;
-      v2n += vnew[k] * vnew[k];
+      const double Dvk = iso * v[k] + gvF * Fb[k];       // (D v)_k with the frozen D
+      const double Fn = (F0[k] + ctau * (xv * v[k] + chiF * Enew * Dvk)) * inv_den;
+      const double vn = (P0[k] - (Fn - F0[k]) * P.inv_c_chat) * inv_rho;
+      v2n += vn * vn;
+      wF_new += vn * Fn;
+      Fv_new += Fb[k] * vn;                               // for v_new . D . v_new
+      F[k] = Fn;                                          // F_new (output candidate)
+      Pm[k] = vn;                                         // v_new (momentum formed below)
     }
 
-    // ---- outer test on the v- and F-dependent part of R ----
-    double wF_old = 0.0, wF_new = 0.0, wDw_new = 0.0;
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      wF_old += v[j] * Fb[j];
-      wF_new += vnew[j] * Fnew[j];
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < ND; ++k) s += D[j][k] * vnew[k];
-      wDw_new += vnew[j] * s;
-    }
-    double W_old = (2.0 * chiE - chiF) * wF_old * P.inv_c2;
+    // ---- outer test on the v- and F-dependent part of R (eq. Rnew) ----
+    double W_old = (2.0 * chiE - chiF) * vF * P.inv_c2;
     double W_new = (2.0 * chiE - chiF) * wF_new * P.inv_c2;
     if (o2) {
       const double b2n = v2n * P.inv_c2;
       const double Tq = (Egas - 0.5 * rho * v2n) * inv_Cv;
       const double Tq2 = Tq * Tq;
+      const double wDw_new = iso * v2n + g * Fv_new * Fv_new;
       W_old += (chiP * Bn - chiE * Enew) * 0.5 * b2 + (chiF - chiE) * (b2 * Enew + Enew * vDv * P.inv_c2);
       W_new += (chiP * ar * Tq2 * Tq2 - chiE * Enew) * 0.5 * b2n +
                (chiF - chiE) * (b2n * Enew + Enew * wDw_new * P.inv_c2);
@@ -298,8 +277,8 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     W_new *= ctau;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
-      v[k] = vnew[k];
-      Fb[k] = Fnew[k];
+      v[k] = Pm[k];
+      Fb[k] = F[k];
     }
     Eb = Enew;
     R = Enew - E0;
@@ -307,20 +286,21 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     if (dW <= P.outer_rtol * fabs(W_old) || dW <= P.outer_rtol * fabs(R)) break;
   }
 
-  if (status == 0u) {
-    double p2 = 0.0;
+  // outputs: F holds F_new, momentum from conservation
+  double p2 = 0.0;
 #pragma unroll
-    for (int k = 0; k < ND; ++k) p2 += Pnew[k] * Pnew[k];
+  for (int k = 0; k < ND; ++k) {
+    Pm[k] = P0[k] - (Fb[k] - F0[k]) * P.inv_c_chat;
+    p2 += Pm[k] * Pm[k];
+  }
+  if (status == 0u) {
     const double eint = Egas - 0.5 * p2 * inv_rho;
     if (!(eint > 0.0) || !(Enew > 0.0)) status |= ERR_NONPHYS;
   }
   E = Enew;
   Eg = Egas;
 #pragma unroll
-  for (int k = 0; k < ND; ++k) {
-    F[k] = Fnew[k];
-    Pm[k] = Pnew[k];
-  }
+  for (int k = 0; k < ND; ++k) F[k] = Fb[k];
   return status;
 }
 

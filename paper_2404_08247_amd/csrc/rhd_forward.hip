@@ -37,7 +37,7 @@ constexpr int NTHREADS = 256;
 #define RHD_ZCHUNK 16
 #endif
 #ifndef RHD_MIN_BLOCKS
-#define RHD_MIN_BLOCKS 2048
+#define RHD_MIN_BLOCKS 1024
 #endif
 #ifndef RHD_XCD_REMAP
 #define RHD_XCD_REMAP 1
@@ -493,7 +493,7 @@ static hipError_t launch_nd(const DevParams& P, const double* ys, const double* 
     // enough workgroups to fill 256 CUs several times, chunks of >= 8 planes
     const long long cols = (long long)gxn * gyn;
     zchunk = RHD_ZCHUNK;
-    while (zchunk > 4 && cols * ((nz + zchunk - 1) / zchunk) < RHD_MIN_BLOCKS) zchunk /= 2;
+    while (zchunk > 8 && cols * ((nz + zchunk - 1) / zchunk) < RHD_MIN_BLOCKS) zchunk /= 2;
     if (zchunk > nz) zchunk = nz;
   }
   const int gzn = (nz + zchunk - 1) / zchunk;
