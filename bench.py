@@ -25,6 +25,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "k_stage_c2_128cubed_fp64.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("rhd_forward.hip", "rhd_device.hpp", "rhd_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2404_08247_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None
+    if that summary was taken on different kernel sources."""
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if line.startswith("kernel_source_sha256:"):
+            vals["hash"] = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch "):
+            k, v = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
+            vals[k.strip()] = float(v)
+    if vals.get("hash") != kernel_source_hash():
+        return None
+    return vals.get(kernel)
 
 
 def stage_bytes_per_cell(ndim):
@@ -163,6 +192,7 @@ def main():
         kname, kb, kt = "k_stage<3,STAGE2>", b2, t2
     else:
         kname, kb, kt = "k_stage<3,STAGE1>", b1, t1
+    traffic = measured_traffic(kname) if args.precision == "fp64" else None
     achieved = kb * cells / kt / 1e9
     print(f"[bench] stage1 {t1 * 1e6:.1f} us  stage2 {t2 * 1e6:.1f} us  wall/step "
           f"{wall / args.steps * 1e6:.1f} us", file=sys.stderr, flush=True)
@@ -202,7 +232,9 @@ def main():
                    "steps_per_call": args.steps},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_cell": kb,
+                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 "
+                     "FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": kb * cells, "bytes_per_cell": kb,
                      "avg_launch_us": kt * 1e6},
         "cpu_baseline": cpu,
     }
