@@ -58,6 +58,7 @@ typedef enum {
 enum { RHD_BC_PERIODIC = 0, RHD_BC_REFLECT = 1 };
 enum { RHD_CLOSURE_M1 = 0, RHD_CLOSURE_EDDINGTON = 1 };
 enum { RHD_FP64 = 0, RHD_MIXED = 1 };
+enum { RHD_SCHEME_PDARS = 0, RHD_SCHEME_RK2SSP = 1 };
 
 typedef struct {
   int32_t ndim;          /* 1, 2 or 3 */
@@ -76,7 +77,9 @@ typedef struct {
                             flux-divergence accumulation and the source in float64 */
   int32_t newton_maxit;  /* inner Newton iteration cap (>= 1; 50 recommended) */
   int32_t outer_maxit;   /* outer iteration cap (>= 1; 10 recommended); reaching it is not an error */
-  int32_t reserved;      /* must be 0 */
+  int32_t scheme;        /* RHD_SCHEME_PDARS (the paper's IMEX method) or RHD_SCHEME_RK2SSP:
+                            the comparator of Sec. 4.2 (first stage transport only, the
+                            source once at the end with the full dt; forward only) */
   double newton_rtol;    /* Newton stopping tolerance relative to E_gas + (c/chat) E (1e-13 in the paper) */
   double outer_rtol;     /* outer stopping tolerance on the v- and F-dependent part of R (1e-13) */
 } rhd_params;

@@ -42,6 +42,8 @@ class OracleParams(ctypes.Structure):
         ("outer_maxit", ctypes.c_int32),
         ("newton_rtol", ctypes.c_double),
         ("outer_rtol", ctypes.c_double),
+        ("scheme", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -105,6 +107,8 @@ def make_params(p: dict) -> OracleParams:
     op.outer_maxit = int(p.get("outer_maxit", 10))
     op.newton_rtol = float(p.get("newton_rtol", 1e-13))
     op.outer_rtol = float(p.get("outer_rtol", 1e-13))
+    op.scheme = {"pdars": 0, "rk2ssp": 1}[p.get("scheme", "pdars")]
+    op.pad_ = 0
     return op
 
 

@@ -64,6 +64,8 @@ typedef struct {
   int32_t outer_maxit;
   double newton_rtol;  // epsilon of the Newton test (1e-13 in the paper)
   double outer_rtol;   // tolerance of the outer test (1e-13 in the paper)
+  int32_t scheme;      // 0 = IMEX PD-ARS (the paper's method), 1 = RK2-SSP comparator
+  int32_t pad_;
 } oracle_params;
 }
 
@@ -568,7 +570,10 @@ static void apply_source(const oracle_params* p, const Grid& g, S* y, const S* r
   }
 }
 
-// One PD-ARS step (O1), eq. (imex1)-(imex2).
+// One step. scheme 0: PD-ARS, eq. (imex1)-(imex2). scheme 1: the RK2-SSP
+// comparator of Sec. 4.2 (transport-only first stage, eq. ssp-f1, the source
+// once at the end with the full dt): y^{n+1/2} = y^n + dt s(y^n);
+// y(t) = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2}); y^{n+1} = Src(y(t), dt).
 template <class S>
 static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho, const S* kP,
                        const S* kF, double dt, std::vector<S>& yh, std::vector<S>& s, int* status,
@@ -580,7 +585,7 @@ static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho
   for (int64_t q = 0; q < M; ++q) yh[q] = y[q];
   for (int r = 0; r < nr; ++r)
     for (int64_t c = 0; c < g.N; ++c) yh[(int64_t)r * g.N + c] = y[(int64_t)r * g.N + c] + S(dt) * s[(int64_t)r * g.N + c];
-  apply_source(p, g, yh.data(), rho, kP, kF, dt, status, fail_cell, nullptr, nullptr);
+  if (p->scheme == 0) apply_source(p, g, yh.data(), rho, kP, kF, dt, status, fail_cell, nullptr, nullptr);
   // stage 2: y(t) = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2}); y^{n+1} = Src(y(t), theta = 1/2)
   transport(p, g, yh.data(), s.data());
   for (int64_t q = 0; q < M; ++q) {
@@ -589,7 +594,8 @@ static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho
     if (r < nr) comb = comb + S(0.5 * dt) * s[q];
     y[q] = comb;
   }
-  apply_source(p, g, y, rho, kP, kF, 0.5 * dt, status, fail_cell, nullptr, nullptr);
+  apply_source(p, g, y, rho, kP, kF, p->scheme == 0 ? 0.5 * dt : dt, status, fail_cell, nullptr,
+               nullptr);
 }
 
 // ---------------------------------------------------------------------------

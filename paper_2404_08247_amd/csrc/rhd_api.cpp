@@ -81,7 +81,7 @@ std::string validate(const rhd_params* p) {
   if (p->precision != RHD_FP64 && p->precision != RHD_MIXED) return "unknown precision";
   if (p->newton_maxit < 1 || p->newton_maxit > 100000) return "newton_maxit out of range";
   if (p->outer_maxit < 1 || p->outer_maxit > 100000) return "outer_maxit out of range";
-  if (p->reserved != 0) return "reserved must be 0";
+  if (p->scheme != RHD_SCHEME_PDARS && p->scheme != RHD_SCHEME_RK2SSP) return "unknown scheme";
   if (!(p->newton_rtol > 0.0) || !std::isfinite(p->newton_rtol)) return "newton_rtol must be > 0";
   if (!(p->outer_rtol >= 0.0) || !std::isfinite(p->outer_rtol)) return "outer_rtol must be >= 0";
   return "";
@@ -147,6 +147,7 @@ rhd::DevParams make_dev(const rhd_params* p, bool alias) {
   d.newton_rtol = p->newton_rtol;
   d.outer_rtol = p->outer_rtol;
   d.kF_alias = alias ? 1 : 0;
+  d.scheme = p->scheme;
   return d;
 }
 
@@ -357,6 +358,8 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
   if (state0 == lambda) return set_err(h, RHD_EINVAL, -1, "state0 and lambda must not alias");
   if (!h->dp.kF_alias && !g_kappa_F)
     return set_err(h, RHD_EINVAL, -1, "a separate kappa_F needs g_kappa_F");
+  if (h->p.scheme != RHD_SCHEME_PDARS)
+    return set_err(h, RHD_EINVAL, -1, "the adjoint is available for the PD-ARS scheme only");
   for (int d = 0; d < h->p.ndim; ++d)
     if (h->p.bc[d] != RHD_BC_PERIODIC)
       return set_err(h, RHD_EINVAL, -1, "the adjoint supports periodic axes only");

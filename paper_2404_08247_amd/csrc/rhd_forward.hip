@@ -401,7 +401,12 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
         for (int k2 = 0; k2 < ND; ++k2) Pm[k2] = 0.5 * (pre[3 + 2 * ND + k2] + pre[1 + k2]);
         tau = hdt;
       }
-      const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, tau);
+      // RK2-SSP comparator: transport only in stage 1, the source once at the end
+      // of the step with the full dt (PD-ARS: dt in stage 1, dt/2 in stage 2)
+      if (P.scheme == 1) tau = dt;
+      const unsigned st = (MODE == MODE_STAGE1 && P.scheme == 1)
+                              ? 0u
+                              : source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, tau);
       if (st) report(err, q, st);
       yw[q] = E;
 #pragma unroll

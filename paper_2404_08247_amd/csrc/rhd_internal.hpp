@@ -25,6 +25,7 @@ struct DevParams {
   double cv_mass;     // kB_over_mu / (gamma - 1)
   double newton_rtol, outer_rtol;
   int kF_alias;       // 1: kappa_F == kappa_P
+  int scheme;         // 0 PD-ARS, 1 RK2-SSP comparator
 };
 
 // Device error word layout (in the workspace): [0] smallest failing cell

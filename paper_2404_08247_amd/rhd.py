@@ -40,7 +40,7 @@ class RHDParams(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("newton_maxit", ctypes.c_int32),
         ("outer_maxit", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
         ("newton_rtol", ctypes.c_double),
         ("outer_rtol", ctypes.c_double),
     ]
@@ -111,7 +111,7 @@ def make_params(p: dict) -> RHDParams:
     rp.precision = {"fp64": 0, "mixed": 1}[p.get("precision", "fp64")]
     rp.newton_maxit = int(p.get("newton_maxit", 50))
     rp.outer_maxit = int(p.get("outer_maxit", 10))
-    rp.reserved = 0
+    rp.scheme = {"pdars": 0, "rk2ssp": 1}[p.get("scheme", "pdars")]
     rp.newton_rtol = float(p.get("newton_rtol", 1e-13))
     rp.outer_rtol = float(p.get("outer_rtol", 1e-13))
     return rp

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_params_struct_layout_matches_header():
     from paper_2404_08247_amd import rhd
     # int32 ndim, closure; int64 n[3]; 6 doubles; int32 bc[3], v_order, precision,
-    # newton_maxit, outer_maxit, reserved; 2 doubles
+    # newton_maxit, outer_maxit, scheme; 2 doubles
     assert ctypes.sizeof(rhd.RHDParams) == 8 + 24 + 48 + 32 + 16
     assert rhd.RHDParams.n.offset == 8
     assert rhd.RHDParams.bc.offset == 80

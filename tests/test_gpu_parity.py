@@ -153,6 +153,10 @@ STEP_CASES = {
     "c3_small_mixed": (lambda: W.config3(n=(48, 24, 20), nsteps=8, precision="mixed"), MIXED_TOL),
     "c5_small_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed"), MIXED_TOL),
     "c2_small_mixed": (lambda: W.config2(n=(40, 36, 20), nsteps=10, precision="mixed"), MIXED_TOL),
+    "c1_rk2ssp": (lambda: W.config1(nsteps=300, scheme="rk2ssp"), FP64_TOL),
+    "c4_small_rk2ssp": (lambda: W.config4(n=(72, 40), nsteps=10, scheme="rk2ssp"), FP64_TOL),
+    "c5_small_rk2ssp_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed",
+                                                scheme="rk2ssp"), MIXED_TOL),
 }
 
 

@@ -180,3 +180,41 @@ def test_dual_tangent_matches_central_differences(orc, cfg):
     # passes until its tangent settles, which moves values by the tolerances)
     y2, _, _ = orc.step(p, y0, w.rho, w.kappa_P, None, w.dt, w.nsteps)
     np.testing.assert_allclose(y, y2, rtol=1e-10, atol=1e-12 * np.abs(y2).max())
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_rk2ssp_comparator_has_the_numerical_diffusion_mode(orc, n):
+    # Sec. 4.2 (eq. ssp-f1, ssp-f2, EErk2): a scheme whose first stage carries the
+    # transport only gains, in the thick limit, a numerical diffusion coefficient
+    # on top of the physical D = chat/(3 chi). With the RK2 average of the two
+    # stages it is chat^2 dt / 6 (the non-dimensional C^2 dt/3 times the 1/2 of
+    # eq. EErk2); PD-ARS has none.
+    out = {}
+    for scheme in ("pdars", "rk2ssp"):
+        p, y, rho, kap, chi, x, Ebg = _diffusion_pulse(n)
+        p["scheme"] = scheme
+        D = p["chat"] / (3.0 * chi)
+        dt = 0.3 * p["dx"] / p["chat"]
+        nsteps = int(round(1.0 / dt))
+        s0 = _second_moment(x, y[0, 0, 0], Ebg)
+        yo, st, _ = orc.step(p, y, rho, kap, None, dt, nsteps)
+        assert st == 0
+        t = nsteps * dt
+        out[scheme] = (_second_moment(x, yo[0, 0, 0], Ebg) - s0) / (2.0 * t) / D
+        num = p["chat"] ** 2 * dt / 6.0 / D
+    assert abs(out["pdars"] - 1.0) < 0.03, out
+    assert abs(out["rk2ssp"] - (1.0 + num)) < 0.03 * (1.0 + num), (out, num)
+
+
+def test_rk2ssp_equals_pdars_without_coupling(orc):
+    # with chi = 0 the source is the identity and both schemes are RK2-SSP
+    p = W.base_params(1, (48,), 1.0, (0,))
+    x = W.cell_centres(48)
+    y = np.zeros((4, 1, 1, 48))
+    y[0] = 1.0 + np.exp(-((x - 0.4) ** 2) / 0.01)
+    y[1] = 0.3 * y[0]
+    y[2] = 1.0
+    zero = np.zeros((1, 1, 48))
+    a, _, _ = orc.step(p, y, np.ones((1, 1, 48)), zero, None, 0.3 / 48, 20)
+    b, _, _ = orc.step(dict(p, scheme="rk2ssp"), y, np.ones((1, 1, 48)), zero, None, 0.3 / 48, 20)
+    assert np.array_equal(a, b)
