@@ -39,6 +39,9 @@ constexpr int NTHREADS = 256;
 #ifndef RHD_MIN_BLOCKS
 #define RHD_MIN_BLOCKS 1024
 #endif
+#ifndef RHD_ZBAL
+#define RHD_ZBAL 1
+#endif
 #ifndef RHD_XCD_REMAP
 #define RHD_XCD_REMAP 1
 #endif
@@ -87,14 +90,19 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   constexpr int NEY = (ND >= 2) ? TX * (TY + 2) : 0;
   constexpr int NFX = (TX + 1) * TY;         // x faces
   constexpr int NFY = (ND >= 2) ? TX * (TY + 1) : 0;
-  constexpr int AREA = (NTILE > NFX + NFY) ? NTILE : NFX + NFY;
-  constexpr int NEYs = NEY > 0 ? NEY : 1;
+  constexpr int NFYs = NFY > 0 ? NFY : 1;
 
   // LDS holds values, edge states and fluxes in double; TT is the arithmetic
-  // type of the limiter and closure (delta form, see rhd_device.hpp).
-  __shared__ double s_area[NR][AREA];        // (E, F) tile, then face fluxes
-  __shared__ double s_exL[NR][NEX], s_exR[NR][NEX];
-  __shared__ double s_eyL[NR][NEYs], s_eyR[NR][NEYs];
+  // type of the limiter and closure (delta form, see rhd_device.hpp). Edge
+  // states are stored per face: s_exR[f] / s_exL[f] are the states left / right
+  // of x face f (the right edge of the cell before it, the left edge of the cell
+  // after it), so a face item reads index f of both and then overwrites it with
+  // the face's flux; the (E, F) tile is free again once the edge states exist.
+  // The last slot of each edge array takes the one edge of a halo cell that no
+  // face needs, so that every edge item stores unconditionally.
+  __shared__ double s_area[NR][NTILE];       // (E, F) tile
+  __shared__ double s_exL[NR][NFX + 1], s_exR[NR][NFX + 1];
+  __shared__ double s_eyL[NR][NFYs + 1], s_eyR[NR][NFYs + 1];
 
   const int tid = threadIdx.x;
   const int tx = tid % TX;
@@ -206,6 +214,27 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     htile = ly * TW + lx;
   }
 
+  // Global loads for plane k+1 are issued while plane k is processed: the
+  // thread's halo position (hv) and, in 3-D, the z-pipeline value of plane k+4
+  // (zn, zn_flip); they are consumed one iteration later.
+  double hv[NR], zn[NR];
+  bool zn_flip = false;
+  auto load_halo = [&](int kk) {
+    if (hoff >= 0) {
+      const long long q = (long long)kk * plane + hoff;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) hv[r] = ys[r * N + q];
+    }
+  };
+  auto load_zplane = [&](int kk) {   // the plane 3 above plane kk
+    const int gz = ghost(kk + 3, nz, P.bc[2], zn_flip);
+    const long long q = cidx(P, cx, cy, gz);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) zn[r] = ys[r * N + q];
+  };
+  load_halo(z0);
+  if constexpr (ND == 3) load_zplane(z0);
+
   for (int k = z0; k < z1; ++k) {
     // ---- source-phase inputs of the own cell, issued before the transport so
     // their latency overlaps it: E_gas and rho v of the stencil state, and for
@@ -243,17 +272,62 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     }
     // halo (3 columns left/right of every row, 3 rows above/below): each thread
     // copies at most one position, whose source offset was resolved once per
-    // block (hoff < 0: no position)
+    // block (hoff < 0: no position); its values were loaded one plane ahead
     if (hoff >= 0) {
-      const long long q = (long long)k * plane + hoff;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        double val = ys[r * N + q];
-        if ((hfx && r == 1) || (hfy && r == 2)) val = -val;
-        s_area[r][htile] = val;
-      }
+      for (int r = 0; r < NR; ++r)
+        s_area[r][htile] = ((hfx && r == 1) || (hfy && r == 2)) ? -hv[r] : hv[r];
+    }
+    double w3n[NR];
+    bool w3_flip = false;
+    if constexpr (ND == 3) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) w3n[r] = zn[r];
+      w3_flip = zn_flip;
+    }
+    if (k + 1 < z1) {
+      load_halo(k + 1);
+      if constexpr (ND == 3) load_zplane(k + 1);
     }
     __syncthreads();
+
+    // ---------------- z face k+1/2 from the register pipeline ----------------
+    // (no LDS: run by half of the waves during the edge phase, in which they
+    // have one item round fewer, and by the other half after the flux phase)
+    double divz[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) divz[r] = 0.0;
+    auto zface = [&]() {
+      if constexpr (ND == 3) {
+        double aL1[NR], fz[NR];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const double w3 = (w3_flip && r == 3) ? -w3n[r] : w3n[r];
+          const TT d12 = TT(zv2[r] - zv1[r]);
+          const TT d23 = TT(w3 - zv2[r]);
+          const TT s2 = mc_slope(d12, d23);                       // cell k+2
+          TT lo = zIo[r];
+          TT ro = TT(0.5) * d12 - (s2 - zs[r]) * TT(1.0 / 6.0);   // cell k+1
+          zIo[r] = TT(-0.5) * d12 - (s2 - zs[r]) * TT(1.0 / 6.0); // left of cell k+2
+          ppm_monotone(lo, ro);
+          aL1[r] = zv1[r] + double(lo);
+          const double aR1 = zv1[r] + double(ro);
+          zs[r] = s2;
+          zc[r] = zv1[r];
+          zv1[r] = zv2[r];
+          zv2[r] = w3;
+          fz[r] = aR1;   // kept until the flux below is formed
+        }
+        double fl3[NR];
+        hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, zaR, aL1, fl3);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          divz[r] = fl3[r] - zfl_prev[r];
+          zfl_prev[r] = fl3[r];
+          zaR[r] = fz[r];
+        }
+      }
+    };
 
     // ---------------- PPM edge states, once per cell ----------------
     // y items first: their count TX (TY + 2) is a multiple of 64 for the 2-D/3-D
@@ -262,113 +336,84 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       if (ND >= 2 && e < NEY) {
         const int col = e % TX, row = e / TX;                // cell y0 + row - 1
         const int base = row * TW + col + HALO;              // = centre - 2 rows
+        // left edge -> face row-1 (below the cell), right edge -> face row
+        const int fl = (row > 0) ? (row - 1) * TX + col : NFY;
+        const int fr = (row <= TY) ? row * TX + col : NFY;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const double* a = &s_area[r][base];
           double l, rr;
           ppm_edges5<TT>(a[0], a[TW], a[2 * TW], a[3 * TW], a[4 * TW], l, rr);
-          s_eyL[r][e] = l;
-          s_eyR[r][e] = rr;
+          s_eyL[r][fl] = l;
+          s_eyR[r][fr] = rr;
         }
       } else {
         const int ex = e - NEY;
         const int row = ex / (TX + 2), col = ex % (TX + 2);  // cell x0 + col - 1
         const int base = (row + (ND >= 2 ? HALO : 0)) * TW + col;  // = centre - 2
+        const int fl = (col > 0) ? row * (TX + 1) + col - 1 : NFX;
+        const int fr = (col <= TX) ? row * (TX + 1) + col : NFX;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const double* a = &s_area[r][base];
           double l, rr;
           ppm_edges5<TT>(a[0], a[1], a[2], a[3], a[4], l, rr);
-          s_exL[r][ex] = l;
-          s_exR[r][ex] = rr;
+          s_exL[r][fl] = l;
+          s_exR[r][fr] = rr;
         }
       }
     }
+    if (RHD_ZBAL && ND == 3 && tid >= NTHREADS / 2) zface();
     __syncthreads();
 
     // ---------------- HLL fluxes, once per face (into the tile's LDS) -------
     // x faces occupy items [0, NFXP) (padded to a multiple of 64 so no wave
     // mixes x and y faces), y faces follow
     constexpr int NFXP = (ND >= 2) ? ((NFX + 63) / 64) * 64 : NFX;
-    for (int f = tid; f < NFXP + NFY; f += NTHREADS) {
+    // item order rotated by half a block, so that the last (partial) round of
+    // face items falls to the waves that run the z face after the edge phase
+    const int ftid = RHD_ZBAL ? (tid + NTHREADS / 2) % NTHREADS : tid;
+    for (int f = ftid; f < NFXP + NFY; f += NTHREADS) {
       double Um[NR], Up[NR], fl[NR];
       if (f < NFXP) {
         if (f < NFX) {
-          const int row = f / (TX + 1), fx = f % (TX + 1);   // between cells fx-1 | fx
-          const int eb = row * (TX + 2) + fx;
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
-            Um[r] = s_exR[r][eb];
-            Up[r] = s_exL[r][eb + 1];
+            Um[r] = s_exR[r][f];
+            Up[r] = s_exL[r][f];
           }
           hll_flux<ND, 0, TT>(clo, c, ch, chc, cch, Um, Up, fl);
 #pragma unroll
-          for (int r = 0; r < NR; ++r) s_area[r][f] = fl[r];
+          for (int r = 0; r < NR; ++r) s_exR[r][f] = fl[r];
         }
       } else if constexpr (ND >= 2) {
         const int f2 = f - NFXP;
-        const int col = f2 % TX, fy = f2 / TX;               // between rows fy-1 | fy
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          Um[r] = s_eyR[r][fy * TX + col];
-          Up[r] = s_eyL[r][(fy + 1) * TX + col];
+          Um[r] = s_eyR[r][f2];
+          Up[r] = s_eyL[r][f2];
         }
         hll_flux<ND, (ND >= 2 ? 1 : 0), TT>(clo, c, ch, chc, cch, Um, Up, fl);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) s_area[r][NFX + f2] = fl[r];
+        for (int r = 0; r < NR; ++r) s_eyR[r][f2] = fl[r];
       }
     }
 
-    // ---------------- z face k+1/2 from the register pipeline ----------------
-    double divz[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) divz[r] = 0.0;
-    if constexpr (ND == 3) {
-      bool flip;
-      const int gz = ghost(k + 3, nz, P.bc[2], flip);
-      const long long q = cidx(P, cx, cy, gz);
-      double aL1[NR], fz[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        double w3 = ys[r * N + q];
-        if (flip && r == 3) w3 = -w3;
-        const TT d12 = TT(zv2[r] - zv1[r]);
-        const TT d23 = TT(w3 - zv2[r]);
-        const TT s2 = mc_slope(d12, d23);                       // cell k+2
-        TT lo = zIo[r];
-        TT ro = TT(0.5) * d12 - (s2 - zs[r]) * TT(1.0 / 6.0);   // cell k+1
-        zIo[r] = TT(-0.5) * d12 - (s2 - zs[r]) * TT(1.0 / 6.0); // left of cell k+2
-        ppm_monotone(lo, ro);
-        aL1[r] = zv1[r] + double(lo);
-        const double aR1 = zv1[r] + double(ro);
-        zs[r] = s2;
-        zc[r] = zv1[r];
-        zv1[r] = zv2[r];
-        zv2[r] = w3;
-        fz[r] = aR1;   // kept until the flux below is formed
-      }
-      double fl3[NR];
-      hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, zaR, aL1, fl3);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        divz[r] = fl3[r] - zfl_prev[r];
-        zfl_prev[r] = fl3[r];
-        zaR[r] = fz[r];
-      }
-    }
+    if (!(RHD_ZBAL && ND == 3 && tid >= NTHREADS / 2)) zface();
     __syncthreads();
 
     // ---------------- divergence of the own cell ----------------
     double s[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      double d = s_area[r][ty * (TX + 1) + tx + 1] - s_area[r][ty * (TX + 1) + tx];
-      if constexpr (ND >= 2)
-        d += s_area[r][NFX + (ty + 1) * TX + tx] - s_area[r][NFX + ty * TX + tx];
+      double d = s_exR[r][ty * (TX + 1) + tx + 1] - s_exR[r][ty * (TX + 1) + tx];
+      if constexpr (ND >= 2) d += s_eyR[r][(ty + 1) * TX + tx] - s_eyR[r][ty * TX + tx];
       d += divz[r];
       s[r] = -d * P.inv_dx;
     }
-    if (k + 1 < z1) __syncthreads();   // LDS is restaged for the next plane
+    // no barrier here: the next plane is staged into s_area, which nobody has
+    // read since the barrier after the edge states; the flux arrays it overwrites
+    // next are written only after the staging barrier
 
     if (!valid) continue;
     const long long q = cidx(P, gx, gy, k);
