@@ -24,6 +24,28 @@ __device__ __forceinline__ double rcp(double x) {
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Square root of an argument in [1, 4] (the closure's sqrt(4 - 3 f^2)), by
+// Goldschmidt's iteration on the hardware reciprocal-square-root estimate
+// (about 24 correct bits): s -> x y, h -> y/2, one step r = 1/2 - s h,
+// s += s r, h += h r (48 bits), then the Newton correction s += h (x - s^2).
+// No range reduction or special cases, which the argument range makes
+// unnecessary; within 0.5 ulp of the correctly rounded root on [1, 4].
+__device__ __forceinline__ double sqrt_1_4(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  return fma(fma(-s, s, x), h, s);
+}
+__device__ __forceinline__ float sqrt_1_4(float x) { return __builtin_amdgcn_sqrtf(x); }
+// The same iteration for 0 or a normal positive argument (the HLL signal
+// speed sqrt(D_dd), D_dd in [0, 1]); zero maps to zero.
+__device__ __forceinline__ double sqrt_nonneg(double x) {
+  return x > 0.0 ? sqrt_1_4(x) : 0.0;
+}
+__device__ __forceinline__ float sqrt_nonneg(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // ---------------------------------------------------------------------------
 // PPM (Colella & Woodward 1984), method-of-lines form: limited slopes,
 // fourth-order interface values, monotonicity constraint on each cell's
@@ -99,7 +121,7 @@ __device__ __forceinline__ void closure_dD(int closure, double c, double E, cons
   const T cE = T(c * E);
   const T r = rcp(fmax(F2, cE * cE));
   const T f2 = F2 * r;
-  const T h = rcp(T(2) + sqrt(T(4) - T(3) * f2));
+  const T h = rcp(T(2) + sqrt_1_4(T(4) - T(3) * f2));
   const T g = T(3) * h * r * Ft[DIR];
 #pragma unroll
   for (int k = 0; k < ND; ++k) dD[k] = g * Ft[k] - ((k == DIR) ? f2 * h : T(0));
@@ -117,7 +139,7 @@ __device__ __forceinline__ void hll_flux(int closure, double c, double chat, dou
   closure_dD<ND, DIR, T>(closure, c, Um[0], Um + 1, dm);
   closure_dD<ND, DIR, T>(closure, c, Up[0], Up + 1, dp);
   const T Ddd = T(1.0 / 3.0) + fmax(dm[DIR], dp[DIR]);
-  const double hS = 0.5 * chat * double(sqrt(Ddd));
+  const double hS = 0.5 * chat * double(sqrt_nonneg(Ddd));
   fl[0] = 0.5 * chat_over_c * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
   const T em = T(Um[0]), ep = T(Up[0]);
   const double half_cc = 0.5 * c_chat;
@@ -153,7 +175,7 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
     const double cE = c * E;
     const double r = rcp(fmax(F2, cE * cE));
     const double f2 = F2 * r;
-    const double h = rcp(2.0 + sqrt(4.0 - 3.0 * f2));
+    const double h = rcp(2.0 + sqrt_1_4(4.0 - 3.0 * f2));
     g = 3.0 * h * r;
     iso -= f2 * h;
   }
