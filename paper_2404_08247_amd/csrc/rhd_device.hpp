@@ -55,11 +55,14 @@ __device__ __forceinline__ float sqrt_nonneg(float x) { return __builtin_amdgcn_
 // in double and then handled in T, so the float path keeps the relative
 // precision of the (small) differences instead of that of the values.
 // ---------------------------------------------------------------------------
+// MC-limited slope from dl = a0 - a(-1), dr = a(+1) - a0: sgn(dc) min(|dc|,
+// 2|dl|, 2|dr|) with dc = (dl + dr)/2 if dl and dr have the same sign, else 0,
+// written as (sgn dl + sgn dr) min(|dl + dr|/4, |dl|, |dr|) (the same value:
+// only power-of-two scalings differ), which needs no compare and select
 template <typename T>
-__device__ __forceinline__ T mc_slope(T dl, T dr) {   // dl = a0 - a(-1), dr = a(+1) - a0
-  const T dc = T(0.5) * (dl + dr);
-  const T lim = fmin(fabs(dc), T(2) * fmin(fabs(dl), fabs(dr)));
-  return (dl * dr > T(0)) ? copysign(lim, dc) : T(0);
+__device__ __forceinline__ T mc_slope(T dl, T dr) {
+  const T m = fmin(T(0.25) * fabs(dl + dr), fmin(fabs(dl), fabs(dr)));
+  return (copysign(T(1), dl) + copysign(T(1), dr)) * m;
 }
 
 // monotonised edge offsets (l, r) of a cell from its raw interface offsets;

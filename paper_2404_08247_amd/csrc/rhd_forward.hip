@@ -58,16 +58,14 @@ __device__ __forceinline__ int ghost(int g, int n, int bc, bool& flip) {
   flip = false;
   if (g >= 0 && g < n) return g;
   if (bc == 0) {
+    if (g < 0 && g + n >= 0) return g + n;   // one period away
+    if (g >= n && g - n < n) return g - n;
     int m = g % n;
     return m < 0 ? m + n : m;
   }
   flip = true;
   int m = (g < 0) ? -1 - g : 2 * n - 1 - g;
   return m < 0 ? 0 : (m >= n ? n - 1 : m);
-}
-
-__device__ __forceinline__ long long cidx(const DevParams& P, int x, int y, int z) {
-  return ((long long)z * P.n[1] + y) * P.n[0] + x;
 }
 
 __device__ __forceinline__ void report(unsigned long long* err, long long cell, unsigned bits) {
@@ -137,6 +135,9 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   const int cx = ghost(gx, nx, P.bc[0], own_fx);
   const int cy = (ND >= 2) ? ghost(gy, ny, P.bc[1], own_fy) : 0;
   const long long N = P.N;
+  const long long plane = (long long)nx * ny;
+  const long long colq = (long long)cy * nx + cx;   // in-range column of this thread
+  const long long outq = (long long)gy * nx + gx;   // own column (valid threads)
 
   const double c = P.c, ch = P.chat, chc = P.chat_over_c, cch = P.c_chat;
   const int clo = P.closure;
@@ -153,7 +154,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     for (int m = 0; m < 6; ++m) {
       bool flip;
       const int gz = ghost(z0 - 3 + m, nz, P.bc[2], flip);
-      const long long q = cidx(P, cx, cy, gz);
+      const long long q = gz * plane + colq;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const double val = ys[r * N + q];
@@ -192,7 +193,6 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   constexpr int NHX = 2 * HALO * TY;
   constexpr int NHY = (ND >= 2) ? 2 * HALO * TX : 0;
   static_assert(NHX + NHY <= NTHREADS, "one halo position per thread");
-  const long long plane = (long long)nx * ny;
   long long hoff = -1;
   int htile = 0;
   bool hfx = false, hfy = false;
@@ -228,7 +228,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   };
   auto load_zplane = [&](int kk) {   // the plane 3 above plane kk
     const int gz = ghost(kk + 3, nz, P.bc[2], zn_flip);
-    const long long q = cidx(P, cx, cy, gz);
+    const long long q = gz * plane + colq;
 #pragma unroll
     for (int r = 0; r < NR; ++r) zn[r] = ys[r * N + q];
   };
@@ -243,7 +243,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     double pre[NPRE];
     double pre_rho = 1.0, pre_kp = 0.0, pre_kf = 0.0;
     if constexpr (MODE != MODE_TRANSPORT) {
-      const long long qc = cidx(P, cx, cy, k);   // in range for every thread
+      const long long qc = k * plane + colq;   // in range for every thread
 #pragma unroll
       for (int m = 0; m <= ND; ++m) pre[m] = ys[(1 + ND + m) * N + qc];
       if constexpr (MODE == MODE_STAGE2) {
@@ -260,7 +260,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
 #pragma unroll
       for (int r = 0; r < NR; ++r) own[r] = zc[r];
     } else {
-      const long long q = cidx(P, cx, cy, k);
+      const long long q = k * plane + colq;
 #pragma unroll
       for (int r = 0; r < NR; ++r) own[r] = ys[r * N + q];
     }
@@ -416,7 +416,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     // next are written only after the staging barrier
 
     if (!valid) continue;
-    const long long q = cidx(P, gx, gy, k);
+    const long long q = k * plane + outq;
     if constexpr (MODE == MODE_TRANSPORT) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) yw[r * N + q] = s[r];
