@@ -65,21 +65,21 @@ __device__ __forceinline__ T mc_slope(T dl, T dr) {
   return (copysign(T(1), dl) + copysign(T(1), dr)) * m;
 }
 
-// monotonised edge offsets (l, r) of a cell from its raw interface offsets;
-// branch-free (selects), so the variables of a cell interleave
+// Monotonised edge offsets (l, r) of a cell from its raw interface offsets.
+// The CW84 constraint in offset form: if l and r do not have opposite signs
+// (the cell is a local extremum) both become 0; otherwise the parabola
+// overshoots exactly when one offset exceeds twice the other in magnitude
+// (del a6 > del^2 <=> |l| > 2|r|, del a6 < -del^2 <=> |r| > 2|l|), and that
+// offset is set to minus twice the other. Both cases at once:
+//   l' = (sgn l - sgn r) min(|l|/2, |r|),  r' = (sgn r - sgn l) min(|r|/2, |l|),
+// branch-free and without selects.
 template <typename T>
 __device__ __forceinline__ void ppm_monotone(T& l, T& r) {
-  const T del = r - l;
-  const T a6 = T(-3) * (l + r);
-  const T del2 = del * del;
-  const T da6 = del * a6;
-  const bool ext = (r * l >= T(0));       // (r - 0)(0 - l) <= 0: local extremum
-  const bool cl = da6 > del2;
-  const bool cr = da6 < -del2;
-  const T nl = cl ? T(-2) * r : l;
-  const T nr = (!cl && cr) ? T(-2) * l : r;
-  l = ext ? T(0) : nl;
-  r = ext ? T(0) : nr;
+  const T t = copysign(T(1), l) - copysign(T(1), r);   // +-2 if opposite signs, else 0
+  const T nl = t * fmin(T(0.5) * fabs(l), fabs(r));
+  const T nr = -t * fmin(T(0.5) * fabs(r), fabs(l));
+  l = nl;
+  r = nr;
 }
 
 // edge states of the middle cell of a[0..4] (double values in, double out)
