@@ -144,6 +144,7 @@ rhd::DevParams make_dev(const rhd_params* p, bool alias) {
   d.inv_c2 = 1.0 / (p->c * p->c);
   d.a_r = p->a_r;
   d.cv_mass = p->kB_over_mu / (p->gamma - 1.0);
+  d.inv_cv_mass = 1.0 / d.cv_mass;
   d.newton_rtol = p->newton_rtol;
   d.outer_rtol = p->outer_rtol;
   d.kF_alias = alias ? 1 : 0;

@@ -23,6 +23,13 @@ __device__ __forceinline__ double rcp(double x) {
   return fma(r, e, r);
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// One refinement step only (relative error about 2^-48): for quantities whose
+// rounding does not reach the result, such as the step length of an iteration
+// whose convergence test uses exact residuals.
+__device__ __forceinline__ double rcp1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
 
 // Square root of an argument in [1, 4] (the closure's sqrt(4 - 3 f^2)), by
 // Goldschmidt's iteration on the hardware reciprocal-square-root estimate
@@ -184,9 +191,10 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
   }
 }
 
+// inv_tch = 1/(tau chat) is passed in (uniform over a launch).
 template <int ND>
 __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double& Eg, double* Pm,
-                                double rho, double kP, double kF, double tau) {
+                                double rho, double kP, double kF, double tau, double inv_tch) {
   const double chiP = rho * kP;
   const double chiE = chiP;
   const double chiF = rho * kF;
@@ -194,9 +202,9 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   const double ch = P.chat;
   const double k_cc = P.c_over_chat;
   const double Cv = rho * P.cv_mass;
-  const double inv_Cv = rcp(Cv);
   const double inv_rho = rcp(rho);
-  const double inv_tch = rcp(tau * ch);
+  const double inv_Cv = inv_rho * P.inv_cv_mass;
+  const double inv_chiE = rcp(chiE);
   const double ar = P.a_r;
   const bool o2 = (P.v_order == 2);
 
@@ -216,10 +224,13 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   double Egas = Eg0;
   double R = 0.0;
   const double tol = P.newton_rtol * (Eg0 + k_cc * E0);
-  // simplified Jacobian (fixed for the call): dF_R/dR and the T^3 factor of dF_R/dE_gas
-  const double J22 = -rcp(ch * chiE * tau) - 1.0;
-  const double J21c = 4.0 * chiP * ar * rcp(chiE * Cv);
+  // simplified Jacobian (fixed for the call): dF_R/dR and the T^3 factor of
+  // dF_R/dE_gas (chi_P / chi_E = 1 for the grey opacities used here)
+  const double J22 = -inv_tch * inv_chiE - 1.0;
+  const double J21c = 4.0 * ar * inv_Cv;
   const double ctau = ch * tau;
+  // order 1: 1/B = 1/chi_E and the flux denominator do not change between passes
+  const double inv_den_o1 = o2 ? 0.0 : rcp(1.0 + ctau * chiF);
   double Enew = E0;
   unsigned status = 0u;
 
@@ -236,9 +247,21 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     double iso, g;
     closure_ig(P.closure, P.c, Eb, F2, iso, g);   // D frozen for this pass
     const double vDv = iso * v2 + g * vF * vF;
-    // R/(tau chat) = A(T) - B E + C  =>  E(E_gas, R) = (A(T) + C - R/(tau chat)) / B
-    const double B = o2 ? chiE * (1.0 + 0.5 * b2) - (chiF - chiE) * (b2 + vDv * P.inv_c2) : chiE;
-    const double inv_B = rcp(B);
+    // R/(tau chat) = A(T) - B E + C  =>  E(E_gas, R) = (A(T) + C - R/(tau chat)) / B.
+    // Order 2 (chi_F = chi_E): B = chi_E a1 with a1 = 1 + beta^2/2, and the flux
+    // update divides by a2 = 1 + chat tau chi_F a1; one reciprocal of a1 a2
+    // gives both 1/B and 1/a2.
+    double inv_B, inv_den;
+    if (o2) {
+      const double a1 = 1.0 + 0.5 * b2;
+      const double a2 = 1.0 + ctau * chiF * a1;
+      const double q = rcp(a1 * a2);
+      inv_B = q * a2 * inv_chiE;
+      inv_den = q * a1;
+    } else {
+      inv_B = inv_chiE;
+      inv_den = inv_den_o1;
+    }
     const double Cc = (2.0 * chiE - chiF) * vF * P.inv_c2;
     const double Aco = chiP * ar * (o2 ? 1.0 + 0.5 * b2 : 1.0);
 
@@ -256,7 +279,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       }
       if (it >= P.newton_maxit) break;
       const double J21 = J21c * T2 * T;
-      const double inv_det = rcp(J22 - k_cc * J21);
+      const double inv_det = rcp1(J22 - k_cc * J21);
       Egas += (k_cc * FR - J22 * FG) * inv_det;
       R += (J21 * FG - FR) * inv_det;
     }
@@ -270,7 +293,6 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     const double Tn = (Egas - KE) * inv_Cv;
     const double Tn2 = Tn * Tn;
     const double Bn = ar * Tn2 * Tn2;
-    const double inv_den = rcp(o2 ? 1.0 + ctau * chiF * (1.0 + 0.5 * b2) : 1.0 + ctau * chiF);
     const double xv = chiP * Bn + (o2 ? 0.0 : (chiF - chiE) * Enew);
     const double gvF = g * vF;
     double v2n = 0.0, wF_new = 0.0, Fv_new = 0.0;

@@ -141,6 +141,10 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
 
   const double c = P.c, ch = P.chat, chc = P.chat_over_c, cch = P.c_chat;
   const int clo = P.closure;
+  // theta dt of this stage's source (PD-ARS: dt in stage 1, dt/2 in stage 2;
+  // the RK2-SSP comparator: dt) and 1/(theta dt chat), the same for every cell
+  const double tau_src = (MODE == MODE_STAGE2 && P.scheme == 0) ? 0.5 * dt : dt;
+  const double inv_tch = rcp(tau_src * ch);
 
   // ---- z pipeline state (ND == 3) ----
   // a_k, a_{k+1}, a_{k+2}; limited slope of cell k+1; raw left interface of
@@ -426,7 +430,6 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     } else {
       // y(t): stage 1 = y^n + dt s(y^n); stage 2 = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2})
       double E, F[ND], Eg, Pm[ND];
-      double tau;
       if constexpr (MODE == MODE_STAGE1) {
         E = own[0] + dt * s[0];
 #pragma unroll
@@ -434,7 +437,6 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
         Eg = pre[0];
 #pragma unroll
         for (int k2 = 0; k2 < ND; ++k2) Pm[k2] = pre[1 + k2];
-        tau = dt;
       } else {
         const double hdt = 0.5 * dt;
         E = 0.5 * (pre[1 + ND] + own[0]) + hdt * s[0];
@@ -444,14 +446,13 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
         Eg = 0.5 * (pre[2 + 2 * ND] + pre[0]);
 #pragma unroll
         for (int k2 = 0; k2 < ND; ++k2) Pm[k2] = 0.5 * (pre[3 + 2 * ND + k2] + pre[1 + k2]);
-        tau = hdt;
       }
       // RK2-SSP comparator: transport only in stage 1, the source once at the end
-      // of the step with the full dt (PD-ARS: dt in stage 1, dt/2 in stage 2)
-      if (P.scheme == 1) tau = dt;
+      // of the step with the full dt
       const unsigned st = (MODE == MODE_STAGE1 && P.scheme == 1)
                               ? 0u
-                              : source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, tau);
+                              : source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, tau_src,
+                                                inv_tch);
       if (st) report(err, q, st);
       yw[q] = E;
 #pragma unroll
@@ -478,7 +479,8 @@ k_source(DevParams P, double* y, const double* __restrict__ rho, const double* _
     Pm[k] = y[(2 + ND + k) * N + q];
   }
   const double kp = kP[q];
-  const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q], tau);
+  const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q], tau,
+                                     rcp(tau * P.chat));
   if (st) report(err, q, st);
   y[q] = E;
   y[(1 + ND) * N + q] = Eg;

@@ -23,6 +23,7 @@ struct DevParams {
   double c_over_chat, chat_over_c, c_chat, inv_c_chat, inv_c2;
   double a_r;
   double cv_mass;     // kB_over_mu / (gamma - 1)
+  double inv_cv_mass; // 1 / cv_mass
   double newton_rtol, outer_rtol;
   int kF_alias;       // 1: kappa_F == kappa_P
   int scheme;         // 0 PD-ARS, 1 RK2-SSP comparator
