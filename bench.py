@@ -10,6 +10,10 @@ HBM before the timed region. Prints one JSON line.
   value     = cells * steps / wall time of the timed rhd_step call (cell-updates/s)
   roofline  = algorithmic HBM bytes of the dominant stage kernel per launch over its
               average duration (hipEvents on the library's stream, same timed region)
+  valu      = the same kernel against the FP64 vector peak (78.6 TFLOP/s): FP64
+              FLOPs per launch from the committed rocprofv3 counter summary over
+              the same live duration (null when the kernel sources have changed
+              since the counters were taken, like roofline.traffic)
   cpu_baseline = the CPU oracle (OpenMP over cells) on a bounded sample of the
               same workload (rank 0, N = 1)
 """
@@ -25,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 PROFILE = os.path.join(ROOT, "profiles", "k_stage_c2_128cubed_fp64.md")
 
 
@@ -37,9 +42,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None
-    if that summary was taken on different kernel sources."""
+def measured_per_launch(kind, kernel):
+    """A per-launch counter figure of `kernel` from the committed counter summary
+    (kind: "traffic_bytes_per_launch" = HBM bytes, "fp64_flops_per_launch" = FP64
+    VALU FLOPs), or None if that summary was taken on different kernel sources."""
     try:
         txt = open(PROFILE).read()
     except OSError:
@@ -48,8 +54,8 @@ def measured_traffic(kernel):
     for line in txt.splitlines():
         if line.startswith("kernel_source_sha256:"):
             vals["hash"] = line.split(":", 1)[1].strip()
-        elif line.startswith("traffic_bytes_per_launch "):
-            k, v = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
+        elif line.startswith(kind + " "):
+            k, v = line[len(kind) + 1:].rsplit(":", 1)
             vals[k.strip()] = float(v)
     if vals.get("hash") != kernel_source_hash():
         return None
@@ -192,7 +198,8 @@ def main():
         kname, kb, kt = "k_stage<3,STAGE2>", b2, t2
     else:
         kname, kb, kt = "k_stage<3,STAGE1>", b1, t1
-    traffic = measured_traffic(kname) if args.precision == "fp64" else None
+    traffic = measured_per_launch("traffic_bytes_per_launch", kname) if args.precision == "fp64" else None
+    flops = measured_per_launch("fp64_flops_per_launch", kname) if args.precision == "fp64" else None
     achieved = kb * cells / kt / 1e9
     print(f"[bench] stage1 {t1 * 1e6:.1f} us  stage2 {t2 * 1e6:.1f} us  wall/step "
           f"{wall / args.steps * 1e6:.1f} us", file=sys.stderr, flush=True)
@@ -236,6 +243,11 @@ def main():
                      "FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes_per_launch": kb * cells, "bytes_per_cell": kb,
                      "avg_launch_us": kt * 1e6},
+        "valu": None if flops is None else {
+            "bound": "alu", "kernel": kname, "fp64_flops_per_launch": flops,
+            "achieved": flops / kt / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": flops / kt / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+            "flops_source": "rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 + _TRANS per dispatch (profiles/)"},
         "cpu_baseline": cpu,
     }
     line.update(extras)
