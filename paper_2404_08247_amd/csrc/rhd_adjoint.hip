@@ -69,45 +69,99 @@ __device__ __forceinline__ double vof(Dd a) { return a.v; }
 template <typename S> __device__ __forceinline__ S smax(S a, S b) { return vof(a) < vof(b) ? b : a; }
 template <typename S> __device__ __forceinline__ S sabs(S a) { return vof(a) < 0.0 ? -a : a; }
 
-struct D5 {
-  double v, d[5];
+// N-tangent dual (value and N partial derivatives).
+template <int N>
+struct DT {
+  double v, d[N];
 };
-__device__ __forceinline__ D5 operator+(const D5& a, const D5& b) {
-  D5 r;
+template <int N> __device__ __forceinline__ DT<N> dtc(double x) {   // constant
+  DT<N> r;
+  r.v = x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = 0.0;
+  return r;
+}
+template <int N> __device__ __forceinline__ DT<N> dtseed(double x, int j) {   // d/dx_j = 1
+  DT<N> r;
+  r.v = x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = (i == j) ? 1.0 : 0.0;
+  return r;
+}
+template <int N> __device__ __forceinline__ DT<N> operator+(const DT<N>& a, const DT<N>& b) {
+  DT<N> r;
   r.v = a.v + b.v;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) r.d[i] = a.d[i] + b.d[i];
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
   return r;
 }
-__device__ __forceinline__ D5 operator-(const D5& a, const D5& b) {
-  D5 r;
+template <int N> __device__ __forceinline__ DT<N> operator-(const DT<N>& a, const DT<N>& b) {
+  DT<N> r;
   r.v = a.v - b.v;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) r.d[i] = a.d[i] - b.d[i];
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
   return r;
 }
-__device__ __forceinline__ D5 operator-(const D5& a) {
-  D5 r;
+template <int N> __device__ __forceinline__ DT<N> operator-(const DT<N>& a) {
+  DT<N> r;
   r.v = -a.v;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) r.d[i] = -a.d[i];
+  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
   return r;
 }
-__device__ __forceinline__ D5 operator*(double a, const D5& b) {
-  D5 r;
+template <int N> __device__ __forceinline__ DT<N> operator*(double a, const DT<N>& b) {
+  DT<N> r;
   r.v = a * b.v;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) r.d[i] = a * b.d[i];
+  for (int i = 0; i < N; ++i) r.d[i] = a * b.d[i];
   return r;
 }
-__device__ __forceinline__ double vof(const D5& a) { return a.v; }
-__device__ __forceinline__ D5 d5zero() {
-  D5 r;
-  r.v = 0.0;
+template <int N> __device__ __forceinline__ DT<N> operator*(const DT<N>& a, double b) {
+  return b * a;
+}
+template <int N> __device__ __forceinline__ DT<N> operator*(const DT<N>& a, const DT<N>& b) {
+  DT<N> r;
+  r.v = a.v * b.v;
 #pragma unroll
-  for (int i = 0; i < 5; ++i) r.d[i] = 0.0;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
   return r;
 }
+template <int N> __device__ __forceinline__ DT<N> operator+(const DT<N>& a, double b) {
+  DT<N> r = a;
+  r.v += b;
+  return r;
+}
+template <int N> __device__ __forceinline__ DT<N> operator+(double a, const DT<N>& b) {
+  return b + a;
+}
+template <int N> __device__ __forceinline__ DT<N> operator-(double a, const DT<N>& b) {
+  return (-b) + a;
+}
+template <int N> __device__ __forceinline__ DT<N> operator/(double a, const DT<N>& b) {
+  const double q = a / b.v;
+  const double s = -q / b.v;
+  DT<N> r;
+  r.v = q;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = s * b.d[i];
+  return r;
+}
+template <int N> __device__ __forceinline__ DT<N> dsqrt(const DT<N>& a) {
+  const double sq = sqrt(a.v);
+  const double f = sq > 0.0 ? 0.5 / sq : 0.0;
+  DT<N> r;
+  r.v = sq;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = f * a.d[i];
+  return r;
+}
+template <int N> __device__ __forceinline__ double vof(const DT<N>& a) { return a.v; }
+template <int N> __device__ __forceinline__ DT<N> sabs(const DT<N>& a) { return a.v < 0.0 ? -a : a; }
+template <> __device__ __forceinline__ DT<3> mk0<DT<3>>(double x) { return dtc<3>(x); }
+template <> __device__ __forceinline__ DT<4> mk0<DT<4>>(double x) { return dtc<4>(x); }
+template <> __device__ __forceinline__ DT<2> mk0<DT<2>>(double x) { return dtc<2>(x); }
+using D5 = DT<5>;
+__device__ __forceinline__ D5 d5zero() { return dtc<5>(0.0); }
 
 // PPM (same method as the forward) on a piecewise-linear scalar type: the
 // tangents of the active branch are carried along.
@@ -126,7 +180,6 @@ __device__ __forceinline__ S slope_s(S dl, S dr, S zero) {
   }
   return vof(dc) < 0.0 ? -m : m;
 }
-__device__ __forceinline__ D5 sabs(const D5& a) { return a.v < 0.0 ? -a : a; }
 
 // edge offsets (from the middle value) of the middle cell of a0..a4
 template <typename S>
@@ -152,29 +205,33 @@ __device__ __forceinline__ void ppm_edges_s(const S& a0, const S& a1, const S& a
   r = a2 + ro;
 }
 
+// Row DIR of the closure tensor, D_DIR,k(U) for k < ND, U = (E, F_1..F_ND), on a
+// generic scalar type (same formulas as the forward).
+template <int ND, int DIR, typename S>
+__device__ __forceinline__ void closure_row_s(const DevParams& P, const S* U, S* Dr) {
+  if (P.closure == 1) {
+#pragma unroll
+    for (int k = 0; k < ND; ++k) Dr[k] = (k == DIR) ? mk0<S>(1.0 / 3.0) : mk0<S>(0.0);
+    return;
+  }
+  S F2 = mk0<S>(0.0);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) F2 = F2 + U[1 + k] * U[1 + k];
+  const S cE = P.c * U[0];
+  const S r = 1.0 / smax(F2, cE * cE);
+  const S f2 = F2 * r;
+  const S h = 1.0 / (2.0 + dsqrt(4.0 - 3.0 * f2));
+  const S g = 3.0 * h * r * U[1 + DIR];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) Dr[k] = g * U[1 + k] + ((k == DIR) ? (1.0 / 3.0) - f2 * h : mk0<S>(0.0));
+}
+
 // HLL flux along DIR on a generic scalar type (same formulas as the forward).
 template <int ND, int DIR, typename S>
 __device__ void hll_flux_s(const DevParams& P, const S* Um, const S* Up, S* fl) {
   S Dm[ND], Dp[ND];
-  auto row = [&](const S* U, S* Dr) {
-    if (P.closure == 1) {
-#pragma unroll
-      for (int k = 0; k < ND; ++k) Dr[k] = (k == DIR) ? mk0<S>(1.0 / 3.0) : mk0<S>(0.0);
-      return;
-    }
-    S F2 = mk0<S>(0.0);
-#pragma unroll
-    for (int k = 0; k < ND; ++k) F2 = F2 + U[1 + k] * U[1 + k];
-    const S cE = P.c * U[0];
-    const S r = 1.0 / smax(F2, cE * cE);
-    const S f2 = F2 * r;
-    const S h = 1.0 / (2.0 + dsqrt(4.0 - 3.0 * f2));
-    const S g = 3.0 * h * r * U[1 + DIR];
-#pragma unroll
-    for (int k = 0; k < ND; ++k) Dr[k] = g * U[1 + k] + ((k == DIR) ? (1.0 / 3.0) - f2 * h : mk0<S>(0.0));
-  };
-  row(Um, Dm);
-  row(Up, Dp);
+  closure_row_s<ND, DIR, S>(P, Um, Dm);
+  closure_row_s<ND, DIR, S>(P, Up, Dp);
   const S hS = (0.5 * P.chat) * dsqrt(smax(Dm[DIR], Dp[DIR]));
   fl[0] = (0.5 * P.chat_over_c) * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
 #pragma unroll
@@ -259,12 +316,15 @@ __device__ __forceinline__ long long nbr(const DevParams& P, long long q, int di
   return (z * ny + y) * nx + x;
 }
 
-// Src adjoint: lam <- A^{-T} lam at the converged cell state z; g_kappa += tau (df/dkappa)^T lam.
+// Src adjoint: mu = A^{-T} lam at the converged cell state z, written back to lam;
+// g_kappa += tau (df/dkappa)^T mu; and the vector updates that follow it in the
+// reverse step: o1 = a1 mu (if o1), o2 = a2 mu + b2 o2 (if o2).
 template <int ND>
 __global__ void __launch_bounds__(ATHREADS)
 k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
           const double* __restrict__ rho, const double* __restrict__ kP,
-          const double* __restrict__ kF, double tau, double* gkP, double* gkF) {
+          const double* __restrict__ kF, double tau, double* gkP, double* gkF,
+          double* __restrict__ o1, double a1, double* __restrict__ o2, double a2, double b2) {
   constexpr int M = 2 + 2 * ND;
   const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
   if (q >= P.N) return;
@@ -275,8 +335,18 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
     z[j] = zs[j * N + q];
     lv[j] = lam[j * N + q];
   }
+  auto outputs = [&](const double* mu) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      if (o1) o1[i * N + q] = a1 * mu[i];
+      if (o2) o2[i * N + q] = a2 * mu[i] + (b2 == 0.0 ? 0.0 : b2 * o2[i * N + q]);
+    }
+  };
   const double rq = rho[q], kp = kP[q], kf = P.kF_alias ? kp : kF[q];
-  if (rq * kp == 0.0 && rq * kf == 0.0) return;   // source is the identity there
+  if (rq * kp == 0.0 && rq * kf == 0.0) {   // source is the identity there: mu = lam
+    outputs(lv);
+    return;
+  }
 
   // scales of the unknowns (conditioning of the dense solve)
   double sc[M];
@@ -391,6 +461,7 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   }
 #pragma unroll
   for (int i = 0; i < M; ++i) lam[i * N + q] = mu[i];
+  outputs(mu);
 }
 
 // Face adjoint along DIR: for face i+1/2 (owned by cell i), fm[0..NR) = (dPhi/dU-)^T phi,
@@ -419,19 +490,50 @@ k_face_adj(DevParams P, const double* __restrict__ y, const double* __restrict__
     ppm_edges_s<double>(a[1], a[2], a[3], a[4], a[5], l, rr, 0.0);
     Up[r] = l;                                    // left edge of cell i+1
   }
+  // phi^T dPhi/dU-+ of the HLL flux
+  //   Phi_0 = (chat/c)(F-_D + F+_D)/2 - hS (E+ - E-),
+  //   Phi_1+k = c chat (E- D-_Dk + E+ D+_Dk)/2 - hS (F+_k - F-_k),
+  //   hS = chat sqrt(max(D-_DD, D+_DD))/2,
+  // with the closure rows and their partials w.r.t. (E, F) of each side from one
+  // NR-tangent dual evaluation per side.
+  DT<NR> um[NR], up[NR], Dm[ND], Dp[ND];
 #pragma unroll
-  for (int j = 0; j < 2 * NR; ++j) {
-    Dd um[NR], up[NR], fl[NR];
+  for (int r = 0; r < NR; ++r) {
+    um[r] = dtseed<NR>(Um[r], r);
+    up[r] = dtseed<NR>(Up[r], r);
+  }
+  closure_row_s<ND, DIR, DT<NR>>(P, um, Dm);
+  closure_row_s<ND, DIR, DT<NR>>(P, up, Dp);
+  const bool mside = !(Dm[DIR].v < Dp[DIR].v);   // the side max() takes
+  const double Dmax = mside ? Dm[DIR].v : Dp[DIR].v;
+  const double sq = sqrt(Dmax);
+  const double hS = 0.5 * P.chat * sq;
+  const double dhS = sq > 0.0 ? 0.25 * P.chat / sq : 0.0;   // d hS / d D_DD
+  double Sig = 0.0;   // sum_r phi_r (U+_r - U-_r)
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      um[r] = mk(Um[r], (j == r) ? 1.0 : 0.0);
-      up[r] = mk(Up[r], (j == NR + r) ? 1.0 : 0.0);
+  for (int r = 0; r < NR; ++r) Sig += phi[r] * (Up[r] - Um[r]);
+  const double hcc = 0.5 * P.c_chat;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double tm = 0.0, tp = 0.0;   // sum_k phi_1+k d(E D_Dk)/dU_r on each side
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      tm += phi[1 + k] * (Um[0] * Dm[k].d[r] + (r == 0 ? Dm[k].v : 0.0));
+      tp += phi[1 + k] * (Up[0] * Dp[k].d[r] + (r == 0 ? Dp[k].v : 0.0));
     }
-    hll_flux_s<ND, DIR, Dd>(P, um, up, fl);
-    double acc = 0.0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc += phi[r] * fl[r].d;
-    fm[j * N + q] = acc;
+    double gm = hcc * tm + hS * phi[r];
+    double gp = hcc * tp - hS * phi[r];
+    if (r == 1 + DIR) {
+      gm += 0.5 * P.chat_over_c * phi[0];
+      gp += 0.5 * P.chat_over_c * phi[0];
+    }
+    if (mside) {
+      gm -= Sig * dhS * Dm[DIR].d[r];
+    } else {
+      gp -= Sig * dhS * Dp[DIR].d[r];
+    }
+    fm[r * N + q] = gm;
+    fm[(NR + r) * N + q] = gp;
   }
 }
 
@@ -484,14 +586,6 @@ k_gather_adj(DevParams P, const double* __restrict__ C, double* __restrict__ out
     for (int o = 0; o < 5; ++o) acc += C[(o * NR + r) * N + src[o]];
     out[r * N + q] += acc;
   }
-}
-
-// out = a x (+ b out)
-__global__ void __launch_bounds__(ATHREADS)
-k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * ATHREADS + threadIdx.x;
-  if (i >= n) return;
-  out[i] = a * x[i] + (b == 0.0 ? 0.0 : b * out[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,20 +644,17 @@ static hipError_t adjoint_nd(const AdjointArgs& A) {
   double* Ln = A.lam_c;
   e = hipMemcpyAsync(Lc, A.lambda, M * sizeof(double), hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
-  const unsigned nbc = blocks_for(N), nbv = blocks_for(M);
+  const unsigned nbc = blocks_for(N);
   const double dt = A.dt;
   for (int n = A.nsteps - 1; n >= 0; --n) {
-    // stage 2 source at y^{n+1}
+    // stage 2 source at y^{n+1}: mu2 in Lc, La = Ln = mu2/2
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, Y(n + 1), Lc, A.rho,
-                       A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF);
-    hipLaunchKernelGGL(k_axpby, dim3(nbv), dim3(ATHREADS), 0, s, M, 0.5, Lc, 0.0, La);
-    hipLaunchKernelGGL(k_axpby, dim3(nbv), dim3(ATHREADS), 0, s, M, 0.5, Lc, 0.0, Ln);
+                       A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF, La, 0.5, Ln, 0.5, 0.0);
     e = transport_vjp<ND>(P, H(n), Lc, 0.5 * dt, La, A.fm, A.C, s);
     if (e != hipSuccess) return e;
-    // stage 1 source at y^{n+1/2}
+    // stage 1 source at y^{n+1/2}: mu1 in La, Ln += mu1
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, H(n), La, A.rho, A.kP,
-                       A.kF, dt, A.gkP, A.gkF);
-    hipLaunchKernelGGL(k_axpby, dim3(nbv), dim3(ATHREADS), 0, s, M, 1.0, La, 1.0, Ln);
+                       A.kF, dt, A.gkP, A.gkF, nullptr, 0.0, Ln, 1.0, 1.0);
     e = transport_vjp<ND>(P, Y(n), La, dt, Ln, A.fm, A.C, s);
     if (e != hipSuccess) return e;
     double* t = Lc;
