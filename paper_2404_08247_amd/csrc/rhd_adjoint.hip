@@ -239,11 +239,13 @@ __device__ void hll_flux_s(const DevParams& P, const S* Um, const S* Up, S* fl) 
     fl[1 + k] = (0.5 * P.c_chat) * (Um[0] * Dm[k] + Up[0] * Dp[k]) - hS * (Up[1 + k] - Um[1 + k]);
 }
 
-// The mixed-frame source terms f(z) (per cell), z = (E, F_1..F_ND, E_gas, p_1..p_ND):
-// f_E = (chat/c)(-c G0), f_F = chat c (-G), f_Egas = c G0, f_p = G, with -c G0 and
-// -G from eq. G0-G1 (order 2; order 1 keeps the O(v/c) terms), P = D(E, F) E.
+// The mixed-frame four-force terms per cell, z = (E, F_1..F_ND, E_gas, p_1..p_ND):
+// g = (-c G0, -G_1..-G_ND) from eq. G0-G1 (order 2; order 1 keeps the O(v/c)
+// terms), P = D(E, F) E. The source terms are f = U g with the constant map
+//   f_E = (chat/c) g_0, f_Egas = -g_0, f_F_k = c chat g_k, f_p_k = -g_k
+// (eq. egupdate-fupdate in RSLA form).
 template <int ND, typename S>
-__device__ void source_rhs(const DevParams& P, const S* z, S rho, S kP, S kF, S* f) {
+__device__ void source_g(const DevParams& P, const S* z, S rho, S kP, S kF, S* gout) {
   const double c = P.c;
   const S chiP = rho * kP, chiE = chiP, chiF = rho * kF;
   const S E = z[0], Eg = z[1 + ND];
@@ -290,31 +292,42 @@ __device__ void source_rhs(const DevParams& P, const S* z, S rho, S kP, S kF, S*
       mG[k] = (-1.0 / c) * chiF * z[1 + k] + (1.0 / c) * chiP * B * v[k] +
               (1.0 / c) * chiF * E * Dv[k] + (1.0 / c) * (chiF - chiE) * E * v[k];
   }
-  f[0] = P.chat_over_c * mcG0;
-  f[1 + ND] = -mcG0;
+  gout[0] = mcG0;
 #pragma unroll
-  for (int k = 0; k < ND; ++k) {
-    f[1 + k] = P.c_chat * mG[k];
-    f[2 + ND + k] = -mG[k];
-  }
+  for (int k = 0; k < ND; ++k) gout[1 + k] = mG[k];
 }
 
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ long long nbr(const DevParams& P, long long q, int dir, int off) {
-  // periodic neighbour of cell q at offset off along axis dir
-  const long long nx = P.n[0], ny = P.n[1], nz = P.n[2];
-  long long x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
-  if (dir == 0) {
-    x = ((x + off) % nx + nx) % nx;
-  } else if (dir == 1) {
-    y = ((y + off) % ny + ny) % ny;
-  } else {
-    z = ((z + off) % nz + nz) % nz;
+// Periodic neighbours of cell q along axis DIR: the cell's coordinate along the
+// axis is found once (one division pair), then each neighbour is q plus a wrapped
+// coordinate offset times the axis stride.
+template <int DIR>
+struct AxisNbr {
+  long long q, stride;
+  int c, n;
+  __device__ __forceinline__ AxisNbr(const DevParams& P, long long q_) : q(q_) {
+    const long long nx = P.n[0], ny = P.n[1];
+    if (DIR == 0) {
+      c = (int)(q % nx);
+      stride = 1;
+    } else if (DIR == 1) {
+      c = (int)((q / nx) % ny);
+      stride = nx;
+    } else {
+      c = (int)(q / (nx * ny));
+      stride = nx * ny;
+    }
+    n = P.n[DIR];
   }
-  return (z * ny + y) * nx + x;
-}
+  __device__ __forceinline__ long long operator()(int off) const {
+    int cc = c + off;
+    while (cc < 0) cc += n;
+    while (cc >= n) cc -= n;
+    return q + (long long)(cc - c) * stride;
+  }
+};
 
 // Src adjoint: mu = A^{-T} lam at the converged cell state z, written back to lam;
 // g_kappa += tau (df/dkappa)^T mu; and the vector updates that follow it in the
@@ -348,115 +361,143 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
     return;
   }
 
-  // scales of the unknowns (conditioning of the dense solve)
-  double sc[M];
-  {
-    double F2 = 0.0, p2 = 0.0;
-#pragma unroll
-    for (int k = 0; k < ND; ++k) {
-      F2 += z[1 + k] * z[1 + k];
-      p2 += z[2 + ND + k] * z[2 + ND + k];
-    }
-    const double sE = fabs(z[0]) > 0.0 ? fabs(z[0]) : 1.0;
-    const double sF = fmax(sqrt(F2), 1e-6 * P.c * sE);
-    const double sP = fmax(sqrt(p2), sF * P.inv_c_chat);
-    sc[0] = sE;
-    sc[1 + ND] = fabs(z[1 + ND]) > 0.0 ? fabs(z[1 + ND]) : 1.0;
-#pragma unroll
-    for (int k = 0; k < ND; ++k) {
-      sc[1 + k] = sF;
-      sc[2 + ND + k] = sP;
-    }
-  }
-  // Mt = (S^-1 A S)^T, A = I - tau df/dz
-  double Mt[M][M];
+  // The rows of df/dz are dependent: df/dz = U G with G = dg/dz (m x M, m = 1 + ND)
+  // and U the constant M x m map above. Hence A^T = I - tau G^T U^T and, by the
+  // push-through identity, mu = A^{-T} lam = lam + tau G^T x with
+  //   K x = U^T lam,   K = I_m - tau (G U)^T,
+  // an m x m system instead of the M x M one.
+  constexpr int m = 1 + ND;
+  const double chc = P.chat_over_c, cch = P.c_chat;
+  double G[m][M];   // column j from a dual evaluation seeded along z_j
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    Dd zd[M], fd[M];
+    Dd zd[M], gd[m];
 #pragma unroll
     for (int i = 0; i < M; ++i) zd[i] = mk(z[i], i == j ? 1.0 : 0.0);
-    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), fd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), gd);
 #pragma unroll
-    for (int i = 0; i < M; ++i)
-      Mt[j][i] = ((i == j) ? 1.0 : 0.0) - tau * fd[i].d * sc[j] / sc[i];
+    for (int i = 0; i < m; ++i) G[i][j] = gd[i].d;
   }
-  // solve Mt muhat = S lam (partial pivoting, fully unrolled: no dynamic indexing)
-  double b[M];
+  // K[k][i] = delta_ki - tau (G U)[i][k]; (G U)[i][0] = (chat/c) G[i][E] - G[i][Egas],
+  // (G U)[i][1+k] = c chat G[i][F_k] - G[i][p_k]; rhs w = U^T lam
+  double K[m][m], w[m];
 #pragma unroll
-  for (int i = 0; i < M; ++i) b[i] = sc[i] * lv[i];
+  for (int i = 0; i < m; ++i) {
+    K[0][i] = ((i == 0) ? 1.0 : 0.0) - tau * (chc * G[i][0] - G[i][1 + ND]);
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
+    for (int k = 0; k < ND; ++k)
+      K[1 + k][i] = ((i == 1 + k) ? 1.0 : 0.0) - tau * (cch * G[i][1 + k] - G[i][2 + ND + k]);
+  }
+  w[0] = chc * lv[0] - lv[1 + ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) w[1 + k] = cch * lv[1 + k] - lv[2 + ND + k];
+  // equilibrate (rows, then columns: the unknowns carry different units), then
+  // Gaussian elimination with partial pivoting, fully unrolled
+  double cs[m];
+#pragma unroll
+  for (int r = 0; r < m; ++r) {
+    double mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < m; ++j) mx = fmax(mx, fabs(K[r][j]));
+    const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+#pragma unroll
+    for (int j = 0; j < m; ++j) K[r][j] *= inv;
+    w[r] *= inv;
+  }
+#pragma unroll
+  for (int j = 0; j < m; ++j) {
+    double mx = 0.0;
+#pragma unroll
+    for (int r = 0; r < m; ++r) mx = fmax(mx, fabs(K[r][j]));
+    cs[j] = mx > 0.0 ? 1.0 / mx : 1.0;
+#pragma unroll
+    for (int r = 0; r < m; ++r) K[r][j] *= cs[j];
+  }
+#pragma unroll
+  for (int k = 0; k < m; ++k) {
     int p = k;
-    double best = fabs(Mt[k][k]);
+    double best = fabs(K[k][k]);
 #pragma unroll
-    for (int i = k + 1; i < M; ++i) {
-      const double a = fabs(Mt[i][k]);
+    for (int i = k + 1; i < m; ++i) {
+      const double a = fabs(K[i][k]);
       if (a > best) {
         best = a;
         p = i;
       }
     }
 #pragma unroll
-    for (int i = k + 1; i < M; ++i) {
+    for (int i = k + 1; i < m; ++i) {
       if (i == p) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-          const double t = Mt[k][j];
-          Mt[k][j] = Mt[i][j];
-          Mt[i][j] = t;
+        for (int j = 0; j < m; ++j) {
+          const double t = K[k][j];
+          K[k][j] = K[i][j];
+          K[i][j] = t;
         }
-        const double t = b[k];
-        b[k] = b[i];
-        b[i] = t;
+        const double t = w[k];
+        w[k] = w[i];
+        w[i] = t;
       }
     }
-    const double inv = 1.0 / Mt[k][k];
+    const double inv = 1.0 / K[k][k];
 #pragma unroll
-    for (int i = k + 1; i < M; ++i) {
-      const double m = Mt[i][k] * inv;
+    for (int i = k + 1; i < m; ++i) {
+      const double f = K[i][k] * inv;
 #pragma unroll
-      for (int j = k + 1; j < M; ++j) Mt[i][j] -= m * Mt[k][j];
-      b[i] -= m * b[k];
+      for (int j = k + 1; j < m; ++j) K[i][j] -= f * K[k][j];
+      w[i] -= f * w[k];
     }
   }
-  double mu[M];
+  double x[m];
 #pragma unroll
-  for (int i = M - 1; i >= 0; --i) {
-    double acc = b[i];
+  for (int i = m - 1; i >= 0; --i) {
+    double acc = w[i];
 #pragma unroll
-    for (int j = i + 1; j < M; ++j) acc -= Mt[i][j] * mu[j];
-    mu[i] = acc / Mt[i][i];
+    for (int j = i + 1; j < m; ++j) acc -= K[i][j] * x[j];
+    x[i] = acc / K[i][i];
   }
 #pragma unroll
-  for (int i = 0; i < M; ++i) mu[i] /= sc[i];   // unscale
+  for (int i = 0; i < m; ++i) x[i] *= cs[i];   // undo the column scaling
+  double mu[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < m; ++i) acc += G[i][j] * x[i];
+    mu[j] = lv[j] + tau * acc;
+  }
 
-  // dJ/dkappa: tau (df/dkappa)^T mu
-  Dd zd[M], fd[M];
+  // dJ/dkappa: tau (df/dkappa)^T mu = tau (dg/dkappa)^T (U^T mu)
+  double um[m];
+  um[0] = chc * mu[0] - mu[1 + ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) um[1 + k] = cch * mu[1 + k] - mu[2 + ND + k];
+  Dd zd[M], gd[m];
 #pragma unroll
   for (int i = 0; i < M; ++i) zd[i] = mk(z[i]);
   if (P.kF_alias) {
-    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kp, gkF ? 0.0 : 1.0), fd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kp, gkF ? 0.0 : 1.0), gd);
     double g = 0.0;
 #pragma unroll
-    for (int i = 0; i < M; ++i) g += fd[i].d * mu[i];
+    for (int i = 0; i < m; ++i) g += gd[i].d * um[i];
     gkP[q] += tau * g;
     if (gkF) {
-      source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kp, 1.0), fd);
+      source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kp, 1.0), gd);
       double h = 0.0;
 #pragma unroll
-      for (int i = 0; i < M; ++i) h += fd[i].d * mu[i];
+      for (int i = 0; i < m; ++i) h += gd[i].d * um[i];
       gkF[q] += tau * h;
     }
   } else {
-    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kf), fd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kf), gd);
     double g = 0.0;
 #pragma unroll
-    for (int i = 0; i < M; ++i) g += fd[i].d * mu[i];
+    for (int i = 0; i < m; ++i) g += gd[i].d * um[i];
     gkP[q] += tau * g;
-    source_rhs<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf, 1.0), fd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf, 1.0), gd);
     double h = 0.0;
 #pragma unroll
-    for (int i = 0; i < M; ++i) h += fd[i].d * mu[i];
+    for (int i = 0; i < m; ++i) h += gd[i].d * um[i];
     if (gkF) gkF[q] += tau * h; else gkP[q] += tau * h;
   }
 #pragma unroll
@@ -475,8 +516,9 @@ k_face_adj(DevParams P, const double* __restrict__ y, const double* __restrict__
   if (q >= P.N) return;
   const long long N = P.N;
   long long nb[6];
+  const AxisNbr<DIR> nbr(P, q);
 #pragma unroll
-  for (int o = 0; o < 6; ++o) nb[o] = nbr(P, q, DIR, o - 2);   // cells i-2..i+3
+  for (int o = 0; o < 6; ++o) nb[o] = nbr(o - 2);   // cells i-2..i+3
   double phi[NR], Um[NR], Up[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -548,8 +590,9 @@ k_ppm_adj(DevParams P, const double* __restrict__ y, const double* __restrict__ 
   if (q >= P.N) return;
   const long long N = P.N;
   long long nb[5];
+  const AxisNbr<DIR> nbr(P, q);
 #pragma unroll
-  for (int o = 0; o < 5; ++o) nb[o] = nbr(P, q, DIR, o - 2);
+  for (int o = 0; o < 5; ++o) nb[o] = nbr(o - 2);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const double mum = fm[r * N + q];            // face i+1/2, w.r.t. aR of cell i
@@ -577,8 +620,9 @@ k_gather_adj(DevParams P, const double* __restrict__ C, double* __restrict__ out
   if (q >= P.N) return;
   const long long N = P.N;
   long long src[5];
+  const AxisNbr<DIR> nbr(P, q);
 #pragma unroll
-  for (int o = 0; o < 5; ++o) src[o] = nbr(P, q, DIR, -(o - 2));
+  for (int o = 0; o < 5; ++o) src[o] = nbr(-(o - 2));
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     double acc = 0.0;
