@@ -16,9 +16,11 @@
 // is the solution of r(z) = 0 with the closure tensor evaluated at z, so this is
 // the derivative of what the forward step computes (to the outer tolerance).
 //
-// Transport adjoint s'(y)^T lambda (gather form, no atomics), per axis d:
+// Transport adjoint s'(y)^T lambda (gather form, no atomics), one fused kernel
+// per axis d, staged in LDS:
 //   1. per face i+1/2: phi = dJ/dPhi = (lambda_{i+1} - lambda_i)/dx, and the
-//      adjoints of its two edge states mu-/mu+ = (dPhi/dU-/+)^T phi (dual seeds);
+//      adjoints of its two edge states mu-/mu+ = (dPhi/dU-/+)^T phi (the closure
+//      and its partials from one multi-tangent dual evaluation per side);
 //   2. per cell i: PPM partials of its edge states w.r.t. the 5 stencil values
 //      (5-tangent duals) times mu- of face i+1/2 and mu+ of face i-1/2, giving
 //      its contribution to each of the cells i-2..i+2;
@@ -300,35 +302,6 @@ __device__ void source_g(const DevParams& P, const S* z, S rho, S kP, S kF, S* g
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-// Periodic neighbours of cell q along axis DIR: the cell's coordinate along the
-// axis is found once (one division pair), then each neighbour is q plus a wrapped
-// coordinate offset times the axis stride.
-template <int DIR>
-struct AxisNbr {
-  long long q, stride;
-  int c, n;
-  __device__ __forceinline__ AxisNbr(const DevParams& P, long long q_) : q(q_) {
-    const long long nx = P.n[0], ny = P.n[1];
-    if (DIR == 0) {
-      c = (int)(q % nx);
-      stride = 1;
-    } else if (DIR == 1) {
-      c = (int)((q / nx) % ny);
-      stride = nx;
-    } else {
-      c = (int)(q / (nx * ny));
-      stride = nx * ny;
-    }
-    n = P.n[DIR];
-  }
-  __device__ __forceinline__ long long operator()(int off) const {
-    int cc = c + off;
-    while (cc < 0) cc += n;
-    while (cc >= n) cc -= n;
-    return q + (long long)(cc - c) * stride;
-  }
-};
-
 // Src adjoint: mu = A^{-T} lam at the converged cell state z, written back to lam;
 // g_kappa += tau (df/dkappa)^T mu; and the vector updates that follow it in the
 // reverse step: o1 = a1 mu (if o1), o2 = a2 mu + b2 o2 (if o2).
@@ -505,39 +478,16 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   outputs(mu);
 }
 
-// Face adjoint along DIR: for face i+1/2 (owned by cell i), fm[0..NR) = (dPhi/dU-)^T phi,
-// fm[NR..2NR) = (dPhi/dU+)^T phi with phi = scale (lam_{i+1} - lam_i)/dx.
+// phi^T dPhi/dU-+ of the HLL flux along DIR between edge states Um | Up:
+//   Phi_0 = (chat/c)(F-_D + F+_D)/2 - hS (E+ - E-),
+//   Phi_1+k = c chat (E- D-_Dk + E+ D+_Dk)/2 - hS (F+_k - F-_k),
+//   hS = chat sqrt(max(D-_DD, D+_DD))/2,
+// with the closure rows and their partials w.r.t. (E, F) of each side from one
+// NR-tangent dual evaluation per side. gm = (dPhi/dU-)^T phi, gp = (dPhi/dU+)^T phi.
 template <int ND, int DIR>
-__global__ void __launch_bounds__(ATHREADS)
-k_face_adj(DevParams P, const double* __restrict__ y, const double* __restrict__ lam, double scale,
-           double* __restrict__ fm) {
+__device__ __forceinline__ void hll_vjp(const DevParams& P, const double* Um, const double* Up,
+                                        const double* phi, double* gm, double* gp) {
   constexpr int NR = 1 + ND;
-  const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
-  if (q >= P.N) return;
-  const long long N = P.N;
-  long long nb[6];
-  const AxisNbr<DIR> nbr(P, q);
-#pragma unroll
-  for (int o = 0; o < 6; ++o) nb[o] = nbr(o - 2);   // cells i-2..i+3
-  double phi[NR], Um[NR], Up[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    phi[r] = scale * (lam[r * N + nb[3]] - lam[r * N + nb[2]]) * P.inv_dx;
-    double a[6];
-#pragma unroll
-    for (int o = 0; o < 6; ++o) a[o] = y[r * N + nb[o]];
-    double l, rr;
-    ppm_edges_s<double>(a[0], a[1], a[2], a[3], a[4], l, rr, 0.0);
-    Um[r] = rr;                                   // right edge of cell i
-    ppm_edges_s<double>(a[1], a[2], a[3], a[4], a[5], l, rr, 0.0);
-    Up[r] = l;                                    // left edge of cell i+1
-  }
-  // phi^T dPhi/dU-+ of the HLL flux
-  //   Phi_0 = (chat/c)(F-_D + F+_D)/2 - hS (E+ - E-),
-  //   Phi_1+k = c chat (E- D-_Dk + E+ D+_Dk)/2 - hS (F+_k - F-_k),
-  //   hS = chat sqrt(max(D-_DD, D+_DD))/2,
-  // with the closure rows and their partials w.r.t. (E, F) of each side from one
-  // NR-tangent dual evaluation per side.
   DT<NR> um[NR], up[NR], Dm[ND], Dp[ND];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -563,72 +513,141 @@ k_face_adj(DevParams P, const double* __restrict__ y, const double* __restrict__
       tm += phi[1 + k] * (Um[0] * Dm[k].d[r] + (r == 0 ? Dm[k].v : 0.0));
       tp += phi[1 + k] * (Up[0] * Dp[k].d[r] + (r == 0 ? Dp[k].v : 0.0));
     }
-    double gm = hcc * tm + hS * phi[r];
-    double gp = hcc * tp - hS * phi[r];
+    gm[r] = hcc * tm + hS * phi[r];
+    gp[r] = hcc * tp - hS * phi[r];
     if (r == 1 + DIR) {
-      gm += 0.5 * P.chat_over_c * phi[0];
-      gp += 0.5 * P.chat_over_c * phi[0];
+      gm[r] += 0.5 * P.chat_over_c * phi[0];
+      gp[r] += 0.5 * P.chat_over_c * phi[0];
     }
     if (mside) {
-      gm -= Sig * dhS * Dm[DIR].d[r];
+      gm[r] -= Sig * dhS * Dm[DIR].d[r];
     } else {
-      gp -= Sig * dhS * Dp[DIR].d[r];
+      gp[r] -= Sig * dhS * Dp[DIR].d[r];
     }
-    fm[r * N + q] = gm;
-    fm[(NR + r) * N + q] = gp;
   }
 }
 
-// PPM adjoint along DIR: contributions of cell i to the stencil cells i-2..i+2,
-// C[(o+2) NR + r] = d aR_i/d a_{i+o} mu-_{i+1/2} + d aL_i/d a_{i+o} mu+_{i-1/2}.
-template <int ND, int DIR>
-__global__ void __launch_bounds__(ATHREADS)
-k_ppm_adj(DevParams P, const double* __restrict__ y, const double* __restrict__ fm,
-          double* __restrict__ C) {
-  constexpr int NR = 1 + ND;
-  const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
-  if (q >= P.N) return;
-  const long long N = P.N;
-  long long nb[5];
-  const AxisNbr<DIR> nbr(P, q);
-#pragma unroll
-  for (int o = 0; o < 5; ++o) nb[o] = nbr(o - 2);
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const double mum = fm[r * N + q];            // face i+1/2, w.r.t. aR of cell i
-    const double mup = fm[(NR + r) * N + nb[1]]; // face i-1/2 (owned by cell i-1), w.r.t. aL of cell i
-    D5 a[5];
-#pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      a[o] = d5zero();
-      a[o].v = y[r * N + nb[o]];
-      a[o].d[o] = 1.0;
-    }
-    D5 l, rr;
-    ppm_edges_s<D5>(a[0], a[1], a[2], a[3], a[4], l, rr, d5zero());
-#pragma unroll
-    for (int o = 0; o < 5; ++o) C[(o * NR + r) * N + q] = rr.d[o] * mum + l.d[o] * mup;
-  }
-}
+// Transport adjoint along DIR, out += scale s_DIR'(y)^T lam restricted to (E, F),
+// one launch per axis. A workgroup owns TL cells along DIR on each of TP lines
+// (lines are neighbours along x, or along y when DIR = 0) and stages in LDS:
+//   y of cells [-5, TL+4] of each line (periodic wrap; lam is read directly),
+//   face adjoints mu-/mu+ of the faces f+1/2, f in [-3, TL+1],
+//   then per variable the PPM contributions C of cells [-2, TL+1] to their five
+//   stencil cells, and gathers them into its own cells (no atomics).
+//   face f+1/2: phi = scale (lam_{f+1} - lam_f)/dx, mu-+ = (dPhi/dU-+)^T phi;
+//   cell c: C_o = d aR_c/d y_{c+o} mu-_{c+1/2} + d aL_c/d y_{c+o} mu+_{c-1/2};
+//   cell j: out_j += sum_o C_o(j - o).
+template <int ND> struct TvjpShape;
+template <> struct TvjpShape<1> { static constexpr int TL = 256, TP = 1; };
+template <> struct TvjpShape<2> { static constexpr int TL = 32, TP = 8; };
+template <> struct TvjpShape<3> { static constexpr int TL = 32, TP = 8; };
+constexpr int TV_NT = 320;
 
-// Gather: out[r][j] += sum_o C[(o+2) NR + r][j - o], o = -2..2.
 template <int ND, int DIR>
-__global__ void __launch_bounds__(ATHREADS)
-k_gather_adj(DevParams P, const double* __restrict__ C, double* __restrict__ out) {
+__global__ void __launch_bounds__(TV_NT)
+k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam, double scale,
+       double* __restrict__ out) {
   constexpr int NR = 1 + ND;
-  const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
-  if (q >= P.N) return;
+  constexpr int TL = TvjpShape<ND>::TL, TP = TvjpShape<ND>::TP;
+  constexpr int NYv = TL + 10, NF = TL + 5, NC = TL + 4;
+  static_assert(NF * TP <= TV_NT && NC * TP <= TV_NT, "one item round per phase");
+  __shared__ double s_y[NR][TP][NYv];
+  __shared__ double s_fm[2 * NR][TP][NF];
+  __shared__ double s_c[5][TP][NC];
+
+  const int tid = threadIdx.x;
   const long long N = P.N;
-  long long src[5];
-  const AxisNbr<DIR> nbr(P, q);
+  const int nx = P.n[0], ny = P.n[1];
+  // axis length, perpendicular line axis, and the strides of the three roles
+  const int na = P.n[DIR];
+  const int pax = (DIR == 0) ? 1 : 0;                  // lines are consecutive along this axis
+  const int np = (ND >= 2) ? P.n[pax] : 1;
+  const long long sa = (DIR == 0) ? 1 : (DIR == 1 ? (long long)nx : (long long)nx * ny);
+  const long long sp = (pax == 0) ? 1 : (long long)nx;
+  // the remaining axis (3-D): z for DIR 0/1, y for DIR 2
+  const long long so = (ND == 3) ? ((DIR == 2) ? (long long)nx : (long long)nx * ny) : 0;
+  const int t0 = blockIdx.x * TL;
+  const int p0 = blockIdx.y * TP;
+  const long long obase = (long long)blockIdx.z * so;
+  auto cell = [&](int a, int p) {   // a wrapped into [0, na)
+    return obase + (long long)a * sa + (long long)(p0 + p) * sp;
+  };
+  auto wrap = [&](int a) {
+    while (a < 0) a += na;
+    while (a >= na) a -= na;
+    return a;
+  };
+
+  // ---- stage y and lam ----
+  for (int it = tid; it < TP * NYv; it += TV_NT) {
+    const int p = it / NYv, t = it % NYv;
+    if (p0 + p < np) {
+      const long long q = cell(wrap(t0 - 5 + t), p);
 #pragma unroll
-  for (int o = 0; o < 5; ++o) src[o] = nbr(-(o - 2));
+      for (int r = 0; r < NR; ++r) s_y[r][p][t] = y[r * N + q];
+    }
+  }
+  __syncthreads();
+
+  // ---- face adjoints: face f (local), between cells f-3 and f-2 of the tile ----
+  if (tid < TP * NF) {
+    const int p = tid / NF, f = tid % NF;
+    if (p0 + p < np) {
+      const long long qb = cell(wrap(t0 - 3 + f), p), qa = cell(wrap(t0 - 2 + f), p);
+      double phi[NR], Um[NR], Up[NR];
 #pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        phi[r] = scale * (lam[r * N + qa] - lam[r * N + qb]) * P.inv_dx;
+        const double* a = &s_y[r][p][f];      // cells f-5 .. f: local y index f .. f+5
+        double l, rr;
+        ppm_edges_s<double>(a[0], a[1], a[2], a[3], a[4], l, rr, 0.0);
+        Um[r] = rr;                           // right edge of the cell below the face
+        ppm_edges_s<double>(a[1], a[2], a[3], a[4], a[5], l, rr, 0.0);
+        Up[r] = l;                            // left edge of the cell above it
+      }
+      double gm[NR], gp[NR];
+      hll_vjp<ND, DIR>(P, Um, Up, phi, gm, gp);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        s_fm[r][p][f] = gm[r];
+        s_fm[NR + r][p][f] = gp[r];
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- per variable: PPM contributions, then the gather ----
   for (int r = 0; r < NR; ++r) {
-    double acc = 0.0;
+    if (tid < TP * NC) {
+      const int p = tid / NC, c = tid % NC;   // cell t0 - 2 + c, local y index c + 3
+      if (p0 + p < np) {
+        const double mum = s_fm[r][p][c + 1];      // its right face, w.r.t. aR
+        const double mup = s_fm[NR + r][p][c];     // its left face, w.r.t. aL
+        D5 a[5];
 #pragma unroll
-    for (int o = 0; o < 5; ++o) acc += C[(o * NR + r) * N + src[o]];
-    out[r * N + q] += acc;
+        for (int o = 0; o < 5; ++o) {
+          a[o] = d5zero();
+          a[o].v = s_y[r][p][c + 1 + o];
+          a[o].d[o] = 1.0;
+        }
+        D5 l, rr;
+        ppm_edges_s<D5>(a[0], a[1], a[2], a[3], a[4], l, rr, d5zero());
+#pragma unroll
+        for (int o = 0; o < 5; ++o) s_c[o][p][c] = rr.d[o] * mum + l.d[o] * mup;
+      }
+    }
+    __syncthreads();
+    if (tid < TP * TL) {
+      const int p = tid / TL, t = tid % TL;
+      if (p0 + p < np && t0 + t < na) {
+        // cell j = t0 + t receives C_o of cell j - (o - 2), local index t + 4 - o
+        double acc = 0.0;
+#pragma unroll
+        for (int o = 0; o < 5; ++o) acc += s_c[o][p][t + 4 - o];
+        out[r * N + cell(t0 + t, p)] += acc;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -637,30 +656,23 @@ k_gather_adj(DevParams P, const double* __restrict__ C, double* __restrict__ out
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(long long n) { return (unsigned)((n + ATHREADS - 1) / ATHREADS); }
 
+template <int ND, int DIR>
+static void launch_tvjp(const DevParams& P, const double* y, const double* lam, double scale,
+                        double* out, hipStream_t s) {
+  constexpr int TL = TvjpShape<ND>::TL, TP = TvjpShape<ND>::TP;
+  const int na = P.n[DIR];
+  const int np = (ND >= 2) ? P.n[DIR == 0 ? 1 : 0] : 1;
+  const int no = (ND == 3) ? P.n[DIR == 2 ? 1 : 2] : 1;
+  const dim3 grid((na + TL - 1) / TL, (np + TP - 1) / TP, no);
+  hipLaunchKernelGGL((k_tvjp<ND, DIR>), grid, dim3(TV_NT), 0, s, P, y, lam, scale, out);
+}
+
 template <int ND>
 static hipError_t transport_vjp(const DevParams& P, const double* y, const double* lam, double scale,
-                                double* out, double* fm, double* C, hipStream_t s) {
-  const unsigned nb = blocks_for(P.N);
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    switch (d) {
-      case 0:
-        hipLaunchKernelGGL((k_face_adj<ND, 0>), dim3(nb), dim3(ATHREADS), 0, s, P, y, lam, scale, fm);
-        hipLaunchKernelGGL((k_ppm_adj<ND, 0>), dim3(nb), dim3(ATHREADS), 0, s, P, y, fm, C);
-        hipLaunchKernelGGL((k_gather_adj<ND, 0>), dim3(nb), dim3(ATHREADS), 0, s, P, C, out);
-        break;
-      case 1:
-        hipLaunchKernelGGL((k_face_adj<ND, (ND > 1 ? 1 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, lam, scale, fm);
-        hipLaunchKernelGGL((k_ppm_adj<ND, (ND > 1 ? 1 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, fm, C);
-        hipLaunchKernelGGL((k_gather_adj<ND, (ND > 1 ? 1 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, C, out);
-        break;
-      default:
-        hipLaunchKernelGGL((k_face_adj<ND, (ND > 2 ? 2 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, lam, scale, fm);
-        hipLaunchKernelGGL((k_ppm_adj<ND, (ND > 2 ? 2 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, y, fm, C);
-        hipLaunchKernelGGL((k_gather_adj<ND, (ND > 2 ? 2 : 0)>), dim3(nb), dim3(ATHREADS), 0, s, P, C, out);
-        break;
-    }
-  }
+                                double* out, hipStream_t s) {
+  launch_tvjp<ND, 0>(P, y, lam, scale, out, s);
+  if constexpr (ND >= 2) launch_tvjp<ND, 1>(P, y, lam, scale, out, s);
+  if constexpr (ND >= 3) launch_tvjp<ND, 2>(P, y, lam, scale, out, s);
   return hipGetLastError();
 }
 
@@ -694,12 +706,12 @@ static hipError_t adjoint_nd(const AdjointArgs& A) {
     // stage 2 source at y^{n+1}: mu2 in Lc, La = Ln = mu2/2
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, Y(n + 1), Lc, A.rho,
                        A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF, La, 0.5, Ln, 0.5, 0.0);
-    e = transport_vjp<ND>(P, H(n), Lc, 0.5 * dt, La, A.fm, A.C, s);
+    e = transport_vjp<ND>(P, H(n), Lc, 0.5 * dt, La, s);
     if (e != hipSuccess) return e;
     // stage 1 source at y^{n+1/2}: mu1 in La, Ln += mu1
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, H(n), La, A.rho, A.kP,
                        A.kF, dt, A.gkP, A.gkF, nullptr, 0.0, Ln, 1.0, 1.0);
-    e = transport_vjp<ND>(P, Y(n), La, dt, Ln, A.fm, A.C, s);
+    e = transport_vjp<ND>(P, Y(n), La, dt, Ln, s);
     if (e != hipSuccess) return e;
     double* t = Lc;
     Lc = Ln;

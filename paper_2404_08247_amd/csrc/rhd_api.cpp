@@ -16,8 +16,6 @@
 struct Layout_ptrs {
   double* states;
   double* lam;
-  double* fm;
-  double* C;
 };
 
 struct rhd_handle {
@@ -88,7 +86,7 @@ std::string validate(const rhd_params* p) {
 }
 
 struct Layout {
-  size_t err, yhalf, partial, adj, states, lam, fm, C, total;
+  size_t err, yhalf, partial, adj, states, lam, total;
 };
 
 Layout layout(const rhd_params* p, int adj_len) {
@@ -105,17 +103,11 @@ Layout layout(const rhd_params* p, int adj_len) {
   off = align_up(off + (size_t)kPartialBlocks * 4 * sizeof(double));
   L.adj = off;
   if (adj_len > 0) {
-    // y^0..y^k and y^{1/2}..y^{k-1/2} of a segment, three adjoint vectors,
-    // per-face edge-state adjoints (2 (1+ndim) N) and per-cell stencil
-    // contributions (5 (1+ndim) N).
+    // y^0..y^k and y^{1/2}..y^{k-1/2} of a segment, and three adjoint vectors
     L.states = off;
     off = align_up(off + (size_t)(2 * adj_len + 1) * nv * N * sizeof(double));
     L.lam = off;
     off = align_up(off + 3 * nv * N * sizeof(double));
-    L.fm = off;
-    off = align_up(off + 2 * nr * N * sizeof(double));
-    L.C = off;
-    off = align_up(off + 5 * nr * N * sizeof(double));
   }
   L.total = off;
   return L;
@@ -219,10 +211,8 @@ rhd_status rhd_create(const rhd_params* p, const double* rho, const double* kapp
   if (adjoint_segment_len > 0) {
     h->adj.states = reinterpret_cast<double*>(h->ws + L.states);
     h->adj.lam = reinterpret_cast<double*>(h->ws + L.lam);
-    h->adj.fm = reinterpret_cast<double*>(h->ws + L.fm);
-    h->adj.C = reinterpret_cast<double*>(h->ws + L.C);
   } else {
-    h->adj = Layout_ptrs{nullptr, nullptr, nullptr, nullptr};
+    h->adj = Layout_ptrs{nullptr, nullptr};
   }
   h->last = RHD_OK;
   h->last_cell = -1;
@@ -383,8 +373,6 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
   A.lam_a = h->adj.lam;
   A.lam_b = h->adj.lam + M;
   A.lam_c = h->adj.lam + 2 * M;
-  A.fm = h->adj.fm;
-  A.C = h->adj.C;
   A.err = h->err;
   A.stream = h->stream;
   e = rhd::launch_adjoint(A);

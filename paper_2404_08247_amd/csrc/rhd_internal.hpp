@@ -62,8 +62,6 @@ struct AdjointArgs {
   double* lam_a;
   double* lam_b;
   double* lam_c;
-  double* fm;             // 2 (1 + ndim) N
-  double* C;              // 5 (1 + ndim) N
   unsigned long long* err;
   hipStream_t stream;
 };
