@@ -82,6 +82,10 @@ typedef struct {
                             source once at the end with the full dt; forward only) */
   double newton_rtol;    /* Newton stopping tolerance relative to E_gas + (c/chat) E (1e-13 in the paper) */
   double outer_rtol;     /* outer stopping tolerance on the v- and F-dependent part of R (1e-13) */
+  double hll_eps_cells;  /* 0: plain HLL (the paper's method). > 0: the Skinner-type correction of
+                            Sec. 4.2 on the energy flux, whose dissipation is multiplied by
+                            eps = min(1, 1/tau) with tau = hll_eps_cells * dx * (chi_F of the two
+                            cells at the face)/2, chi_F = rho kappa_F (forward only) */
 } rhd_params;
 
 /* Bytes of device workspace rhd_create needs for these parameters.
@@ -119,7 +123,8 @@ rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps);
  *     into g_kappa_P.
  * The forward steps are recomputed from state0 inside the call; each local
  * implicit solve is differentiated with the implicit function theorem at its
- * converged state. */
+ * converged state. Returns RHD_EINVAL (nothing launched) for reflecting axes,
+ * the RK2-SSP scheme or hll_eps_cells > 0, which the adjoint does not cover. */
 rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int32_t nsteps,
                             double* lambda, double* g_kappa_P, double* g_kappa_F);
 

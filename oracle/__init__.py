@@ -44,6 +44,7 @@ class OracleParams(ctypes.Structure):
         ("outer_rtol", ctypes.c_double),
         ("scheme", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
+        ("hll_eps_cells", ctypes.c_double),
     ]
 
 
@@ -65,7 +66,7 @@ def lib():
         L.oracle_step.restype = ctypes.c_int
         L.oracle_stage1.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_double, i64p]
         L.oracle_stage1.restype = ctypes.c_int
-        L.oracle_transport.argtypes = [pp, dp, dp]
+        L.oracle_transport.argtypes = [pp, dp, dp, dp, dp]
         L.oracle_transport.restype = None
         L.oracle_source.argtypes = [pp, dp, dp, dp, dp, ctypes.c_double, ip, ip, i64p]
         L.oracle_source.restype = ctypes.c_int
@@ -75,6 +76,8 @@ def lib():
         L.oracle_closure.restype = None
         L.oracle_hll.argtypes = [pp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.oracle_hll.restype = None
+        L.oracle_face_eps.argtypes = [pp, ctypes.c_double, ctypes.c_double]
+        L.oracle_face_eps.restype = ctypes.c_double
         L.oracle_step_dual.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double,
                                        ctypes.c_int, i64p]
         L.oracle_step_dual.restype = ctypes.c_int
@@ -109,6 +112,7 @@ def make_params(p: dict) -> OracleParams:
     op.outer_rtol = float(p.get("outer_rtol", 1e-13))
     op.scheme = {"pdars": 0, "rk2ssp": 1}[p.get("scheme", "pdars")]
     op.pad_ = 0
+    op.hll_eps_cells = float(p.get("hll_eps_cells", 0.0))
     return op
 
 
@@ -142,10 +146,14 @@ def stage1(p: dict, y: np.ndarray, rho, kP, kF, dt: float):
     return yh, st, fc.value
 
 
-def transport(p: dict, y: np.ndarray) -> np.ndarray:
+def transport(p: dict, y: np.ndarray, rho=None, kF=None) -> np.ndarray:
+    """s(y); rho and kF (chi_F = rho kF) are needed only with hll_eps_cells > 0."""
     y = _c(y)
     s = np.zeros_like(y)
-    lib().oracle_transport(ctypes.byref(make_params(p)), _dp(y), _dp(s))
+    rho, kF = _c(rho), _c(kF)
+    if float(p.get("hll_eps_cells", 0.0)) > 0.0 and (rho is None or kF is None):
+        raise ValueError("hll_eps_cells > 0 needs rho and kF")
+    lib().oracle_transport(ctypes.byref(make_params(p)), _dp(y), _dp(s), _dp(rho), _dp(kF))
     return s
 
 
@@ -171,6 +179,10 @@ def ppm_edges(a: np.ndarray):
     aR = np.full_like(a, np.nan)
     lib().oracle_ppm_edges(_dp(a), a.size, _dp(aL), _dp(aR))
     return aL, aR
+
+
+def face_eps(p: dict, chi_a: float, chi_b: float) -> float:
+    return float(lib().oracle_face_eps(ctypes.byref(make_params(p)), float(chi_a), float(chi_b)))
 
 
 def closure(p: dict, ndim: int, E: float, F) -> np.ndarray:

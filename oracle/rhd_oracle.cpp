@@ -66,6 +66,8 @@ typedef struct {
   double outer_rtol;   // tolerance of the outer test (1e-13 in the paper)
   int32_t scheme;      // 0 = IMEX PD-ARS (the paper's method), 1 = RK2-SSP comparator
   int32_t pad_;
+  double hll_eps_cells;  // > 0: Skinner-type eps on the HLL energy dissipation (Sec. 4.2),
+                         // eps = min(1, 1/tau), tau = hll_eps_cells * dx * face chi_F; 0: off
 } oracle_params;
 }
 
@@ -206,8 +208,12 @@ static void ppm_edges(const S* a /* a[-2..2] via a[0..4] */, S& aL, S& aR) {
 //   S = chat sqrt(max(D_dd(U-), D_dd(U+))), S_L = -S, S_R = S (Sec. 4.3: the
 //   uncorrected speed sqrt(f) scaled by chat).
 // ---------------------------------------------------------------------------
+// eps scales the dissipation of the energy component only (Skinner's corrected
+// energy flux, Sec. 4.2: (S_R F_L - S_L F_R + eps S_R S_L (E_R - E_L)) / (S_R - S_L)
+// with S_L = -S_R); eps = 1 is the plain HLL flux.
 template <class S>
-static void hll_flux(const oracle_params* p, int ndim, int d, const S* Um, const S* Up, S* flux) {
+static void hll_flux(const oracle_params* p, int ndim, int d, const S* Um, const S* Up, S* flux,
+                     S eps = S(1.0)) {
   S Dm[3][3], Dp[3][3];
   closure_D(p, ndim, Um[0], Um + 1, Dm);
   closure_D(p, ndim, Up[0], Up + 1, Dp);
@@ -221,7 +227,17 @@ static void hll_flux(const oracle_params* p, int ndim, int d, const S* Um, const
   }
   S smax_ = ch * ssqrt(smax(Dm[d][d], Dp[d][d]));
   for (int q = 0; q < 1 + ndim; ++q)
-    flux[q] = S(0.5) * (phim[q] + phip[q]) - S(0.5) * smax_ * (Up[q] - Um[q]);
+    flux[q] = S(0.5) * (phim[q] + phip[q]) - S(0.5) * (q == 0 ? eps : S(1.0)) * smax_ * (Up[q] - Um[q]);
+}
+
+// Skinner-type eps of the face between cells with flux-mean absorption
+// coefficients chi_a and chi_b: tau = hll_eps_cells * dx * (chi_a + chi_b) / 2,
+// eps = min(1, 1/tau) (1 in the streaming limit, 1/tau in the thick limit).
+template <class S>
+static S face_eps(const oracle_params* p, S chi_a, S chi_b) {
+  if (!(p->hll_eps_cells > 0.0)) return S(1.0);
+  S tau = S(p->hll_eps_cells * p->dx) * S(0.5) * (chi_a + chi_b);
+  return (val(tau) > 1.0) ? S(1.0) / tau : S(1.0);
 }
 
 // Ghost rule (O2): 3 ghost layers along axis d. Periodic: wrap. Reflecting:
@@ -242,8 +258,11 @@ static inline int64_t ghost_index(int64_t i, int64_t n, int bc, bool& flip) {
 
 // s(y) for E and F (O6): s = -sum_d (Phi_{d,i+1/2} - Phi_{d,i-1/2}) / dx.
 // y and s are full SoA state arrays; s of E_gas and momentum is zero.
+// rho, kF (kF NULL: kP) give chi_F = rho kF for the optional eps correction; they
+// may be NULL when hll_eps_cells == 0.
 template <class S>
-static void transport(const oracle_params* p, const Grid& g, const S* y, S* s) {
+static void transport(const oracle_params* p, const Grid& g, const S* y, S* s, const S* rho,
+                      const S* kF) {
   const int nd = g.ndim;
   const int nr = 1 + nd;  // radiation variables E, F_1..F_nd
   for (int64_t q = 0; q < (int64_t)g.nvar * g.N; ++q) s[q] = S(0.0);
@@ -292,7 +311,14 @@ static void transport(const oracle_params* p, const Grid& g, const S* y, S* s) {
             Um[r] = eR[(size_t)(f - 1 + 1) * nr + r];
             Up[r] = eL[(size_t)(f + 1) * nr + r];
           }
-          hll_flux(p, nd, d, Um, Up, &fl[(size_t)f * nr]);
+          S eps = S(1.0);
+          if (p->hll_eps_cells > 0.0) {
+            bool fl_;
+            const int64_t ca = cell(ghost_index(f - 1, nl, p->bc[d], fl_));
+            const int64_t cb = cell(ghost_index(f, nl, p->bc[d], fl_));
+            eps = face_eps(p, rho[ca] * kF[ca], rho[cb] * kF[cb]);
+          }
+          hll_flux(p, nd, d, Um, Up, &fl[(size_t)f * nr], eps);
         }
         for (int64_t t = 0; t < nl; ++t) {
           int64_t c = cell(t);
@@ -580,14 +606,15 @@ static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho
                        int64_t* fail_cell) {
   const int64_t M = (int64_t)g.nvar * g.N;
   const int nr = 1 + g.ndim;
+  const S* kFx = kF ? kF : kP;   // flux-mean opacity for the optional eps correction
   // stage 1: y(t) = y^n + dt s(y^n); y^{n+1/2} = Src(y(t), theta = 1)
-  transport(p, g, y, s.data());
+  transport(p, g, y, s.data(), rho, kFx);
   for (int64_t q = 0; q < M; ++q) yh[q] = y[q];
   for (int r = 0; r < nr; ++r)
     for (int64_t c = 0; c < g.N; ++c) yh[(int64_t)r * g.N + c] = y[(int64_t)r * g.N + c] + S(dt) * s[(int64_t)r * g.N + c];
   if (p->scheme == 0) apply_source(p, g, yh.data(), rho, kP, kF, dt, status, fail_cell, nullptr, nullptr);
   // stage 2: y(t) = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2}); y^{n+1} = Src(y(t), theta = 1/2)
-  transport(p, g, yh.data(), s.data());
+  transport(p, g, yh.data(), s.data(), rho, kFx);
   for (int64_t q = 0; q < M; ++q) {
     int r = (int)(q / g.N);
     S comb = S(0.5) * (y[q] + yh[q]);
@@ -638,7 +665,7 @@ int oracle_stage1(const oracle_params* p, const double* y, double* yh, const dou
   Grid g(p);
   const int64_t M = (int64_t)g.nvar * g.N;
   std::vector<double> s((size_t)M);
-  transport(p, g, y, s.data());
+  transport(p, g, y, s.data(), rho, kF ? kF : kP);
   const int nr = 1 + g.ndim;
   for (int64_t q = 0; q < M; ++q) yh[q] = y[q] + ((q / g.N) < nr ? dt * s[q] : 0.0);
   int status = ORC_OK;
@@ -648,10 +675,12 @@ int oracle_stage1(const oracle_params* p, const double* y, double* yh, const dou
   return status;
 }
 
-// s(y): transport right-hand side for E and F (zero for gas variables).
-void oracle_transport(const oracle_params* p, const double* y, double* s) {
+// s(y): transport right-hand side for E and F (zero for gas variables). rho and
+// kF (chi_F = rho kF) are needed only with hll_eps_cells > 0.
+void oracle_transport(const oracle_params* p, const double* y, double* s, const double* rho,
+                      const double* kF) {
   Grid g(p);
-  transport(p, g, y, s);
+  transport(p, g, y, s, rho, kF);
 }
 
 // Src applied to every cell with theta*dt = tau. iters/outers may be NULL.
@@ -682,6 +711,11 @@ void oracle_closure(const oracle_params* p, int ndim, double E, const double* F,
 void oracle_hll(const oracle_params* p, int ndim, int d, const double* Um, const double* Up,
                 double* flux) {
   hll_flux(p, ndim, d, Um, Up, flux);
+}
+
+// eps of a face between cells with chi_F = chi_a, chi_b (1 when the correction is off).
+double oracle_face_eps(const oracle_params* p, double chi_a, double chi_b) {
+  return face_eps(p, chi_a, chi_b);
 }
 
 // Dual-number step: (y, ty) value and tangent; tangents of rho are zero;

@@ -82,6 +82,8 @@ std::string validate(const rhd_params* p) {
   if (p->scheme != RHD_SCHEME_PDARS && p->scheme != RHD_SCHEME_RK2SSP) return "unknown scheme";
   if (!(p->newton_rtol > 0.0) || !std::isfinite(p->newton_rtol)) return "newton_rtol must be > 0";
   if (!(p->outer_rtol >= 0.0) || !std::isfinite(p->outer_rtol)) return "outer_rtol must be >= 0";
+  if (!(p->hll_eps_cells >= 0.0) || !std::isfinite(p->hll_eps_cells))
+    return "hll_eps_cells must be >= 0 and finite";
   return "";
 }
 
@@ -141,6 +143,7 @@ rhd::DevParams make_dev(const rhd_params* p, bool alias) {
   d.outer_rtol = p->outer_rtol;
   d.kF_alias = alias ? 1 : 0;
   d.scheme = p->scheme;
+  d.eps_dx = p->hll_eps_cells * p->dx;
   return d;
 }
 
@@ -351,6 +354,8 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
     return set_err(h, RHD_EINVAL, -1, "a separate kappa_F needs g_kappa_F");
   if (h->p.scheme != RHD_SCHEME_PDARS)
     return set_err(h, RHD_EINVAL, -1, "the adjoint is available for the PD-ARS scheme only");
+  if (h->p.hll_eps_cells > 0.0)
+    return set_err(h, RHD_EINVAL, -1, "the adjoint does not cover the HLL eps correction");
   for (int d = 0; d < h->p.ndim; ++d)
     if (h->p.bc[d] != RHD_BC_PERIODIC)
       return set_err(h, RHD_EINVAL, -1, "the adjoint supports periodic axes only");

@@ -141,16 +141,18 @@ __device__ __forceinline__ void closure_dD(int closure, double c, double E, cons
 // Phi_E = (chat/c) F_DIR, Phi_Fk = c chat E D_DIR,k, signal speed
 // chat sqrt(max D_DIR,DIR) (the uncorrected speed, Sec. 4.3). The O(1) parts are
 // formed in double, the closure deviation dD in T.
+// eps_e multiplies the dissipation of the energy component (1: plain HLL; the
+// optional Skinner-type correction of Sec. 4.2 passes face_eps()).
 template <int ND, int DIR, typename T>
 __device__ __forceinline__ void hll_flux(int closure, double c, double chat, double chat_over_c,
                                          double c_chat, const double* Um, const double* Up,
-                                         double* fl) {
+                                         double* fl, double eps_e = 1.0) {
   T dm[ND], dp[ND];
   closure_dD<ND, DIR, T>(closure, c, Um[0], Um + 1, dm);
   closure_dD<ND, DIR, T>(closure, c, Up[0], Up + 1, dp);
   const T Ddd = T(1.0 / 3.0) + fmax(dm[DIR], dp[DIR]);
   const double hS = 0.5 * chat * double(sqrt_nonneg(Ddd));
-  fl[0] = 0.5 * chat_over_c * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
+  fl[0] = 0.5 * chat_over_c * (Um[1 + DIR] + Up[1 + DIR]) - eps_e * hS * (Up[0] - Um[0]);
   const T em = T(Um[0]), ep = T(Up[0]);
   const double half_cc = 0.5 * c_chat;
 #pragma unroll
@@ -158,6 +160,14 @@ __device__ __forceinline__ void hll_flux(int closure, double c, double chat, dou
     double iso = (k == DIR) ? (Um[0] + Up[0]) * (1.0 / 3.0) : 0.0;
     fl[1 + k] = half_cc * (iso + double(em * dm[k] + ep * dp[k])) - hS * (Up[1 + k] - Um[1 + k]);
   }
+}
+
+// Skinner-type eps of a face between cells with flux-mean absorption chi_a, chi_b:
+// tau = hll_eps_cells dx (chi_a + chi_b)/2 (eps_dx = hll_eps_cells dx),
+// eps = min(1, 1/tau).
+__device__ __forceinline__ double face_eps(double eps_dx, double chi_a, double chi_b) {
+  const double tau = eps_dx * 0.5 * (chi_a + chi_b);
+  return tau > 1.0 ? rcp(tau) : 1.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -73,7 +73,9 @@ __device__ __forceinline__ void report(unsigned long long* err, long long cell, 
   atomicOr(reinterpret_cast<unsigned int*>(err + 1), bits);
 }
 
-template <int ND, int MODE, typename TT>
+// EPS: the optional Skinner-type eps on the HLL energy flux (a separate
+// instantiation: it stages chi_F = rho kappa_F of the tile in LDS).
+template <int ND, int MODE, typename TT, bool EPS>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(RHD_STAGE_WAVES)))
 k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw,
         const double* __restrict__ rho, const double* __restrict__ kP,
@@ -101,6 +103,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   __shared__ double s_area[NR][NTILE];       // (E, F) tile
   __shared__ double s_exL[NR][NFX + 1], s_exR[NR][NFX + 1];
   __shared__ double s_eyL[NR][NFYs + 1], s_eyR[NR][NFYs + 1];
+  __shared__ double s_chi[EPS ? NTILE : 1];  // chi_F of the tile (EPS only)
 
   const int tid = threadIdx.x;
   const int tx = tid % TX;
@@ -138,6 +141,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   const long long plane = (long long)nx * ny;
   const long long colq = (long long)cy * nx + cx;   // in-range column of this thread
   const long long outq = (long long)gy * nx + gx;   // own column (valid threads)
+  const double* __restrict__ kFv = P.kF_alias ? kP : kF;   // flux-mean opacity
 
   const double c = P.c, ch = P.chat, chc = P.chat_over_c, cch = P.c_chat;
   const int clo = P.closure;
@@ -190,7 +194,14 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       zv1[r] = w[4][r];
       zv2[r] = w[5][r];
     }
-    hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, Um, Up, zfl_prev);
+    double eps0 = 1.0;
+    if constexpr (EPS) {
+      bool fl_;
+      const long long qa = ghost(z0 - 1, nz, P.bc[2], fl_) * plane + colq;
+      const long long qb = (long long)z0 * plane + colq;
+      eps0 = face_eps(P.eps_dx, rho[qa] * kFv[qa], rho[qb] * kFv[qb]);
+    }
+    hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, Um, Up, zfl_prev, eps0);
   }
 
   // halo position of this thread and its source cell within a plane
@@ -282,6 +293,21 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       for (int r = 0; r < NR; ++r)
         s_area[r][htile] = ((hfx && r == 1) || (hfy && r == 2)) ? -hv[r] : hv[r];
     }
+    double chi_k = 0.0, chi_k1 = 0.0;   // chi_F of the own cell at planes k and k+1 (EPS)
+    if constexpr (EPS) {
+      const long long qo = k * plane + colq;
+      chi_k = rho[qo] * kFv[qo];
+      s_chi[(ty + (ND >= 2 ? HALO : 0)) * TW + tx + HALO] = chi_k;
+      if (hoff >= 0) {
+        const long long qh = k * plane + hoff;
+        s_chi[htile] = rho[qh] * kFv[qh];
+      }
+      if constexpr (ND == 3) {
+        bool fl_;
+        const long long q1 = ghost(k + 1, nz, P.bc[2], fl_) * plane + colq;
+        chi_k1 = rho[q1] * kFv[q1];
+      }
+    }
     double w3n[NR];
     bool w3_flip = false;
     if constexpr (ND == 3) {
@@ -323,7 +349,8 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
           fz[r] = aR1;   // kept until the flux below is formed
         }
         double fl3[NR];
-        hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, zaR, aL1, fl3);
+        hll_flux<ND, 2 % ND, TT>(clo, c, ch, chc, cch, zaR, aL1, fl3,
+                                 EPS ? face_eps(P.eps_dx, chi_k, chi_k1) : 1.0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           divz[r] = fl3[r] - zfl_prev[r];
@@ -386,7 +413,13 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
             Um[r] = s_exR[r][f];
             Up[r] = s_exL[r][f];
           }
-          hll_flux<ND, 0, TT>(clo, c, ch, chc, cch, Um, Up, fl);
+          double eps_f = 1.0;
+          if constexpr (EPS) {
+            const int row = f / (TX + 1), fx = f % (TX + 1);   // between cells fx-1 | fx
+            const int b = (row + (ND >= 2 ? HALO : 0)) * TW + fx + HALO;
+            eps_f = face_eps(P.eps_dx, s_chi[b - 1], s_chi[b]);
+          }
+          hll_flux<ND, 0, TT>(clo, c, ch, chc, cch, Um, Up, fl, eps_f);
 #pragma unroll
           for (int r = 0; r < NR; ++r) s_exR[r][f] = fl[r];
         }
@@ -397,7 +430,13 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
           Um[r] = s_eyR[r][f2];
           Up[r] = s_eyL[r][f2];
         }
-        hll_flux<ND, (ND >= 2 ? 1 : 0), TT>(clo, c, ch, chc, cch, Um, Up, fl);
+        double eps_f = 1.0;
+        if constexpr (EPS) {
+          const int col = f2 % TX, fy = f2 / TX;               // between rows fy-1 | fy
+          const int b = (fy + HALO) * TW + col + HALO;
+          eps_f = face_eps(P.eps_dx, s_chi[b - TW], s_chi[b]);
+        }
+        hll_flux<ND, (ND >= 2 ? 1 : 0), TT>(clo, c, ch, chc, cch, Um, Up, fl, eps_f);
 #pragma unroll
         for (int r = 0; r < NR; ++r) s_eyR[r][f2] = fl[r];
       }
@@ -533,7 +572,7 @@ k_totals(DevParams P, const double* __restrict__ y, double* __restrict__ partial
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int ND, int MODE, typename TT>
+template <int ND, int MODE, typename TT, bool EPS>
 static hipError_t launch_nd(const DevParams& P, const double* ys, const double* yo, double* yw,
                             const double* rho, const double* kP, const double* kF, double dt,
                             unsigned long long* err, hipStream_t s) {
@@ -549,7 +588,7 @@ static hipError_t launch_nd(const DevParams& P, const double* ys, const double* 
     if (zchunk > nz) zchunk = nz;
   }
   const int gzn = (nz + zchunk - 1) / zchunk;
-  hipLaunchKernelGGL((k_stage<ND, MODE, TT>), dim3(gxn, gyn, gzn), dim3(NTHREADS), 0, s, P, ys,
+  hipLaunchKernelGGL((k_stage<ND, MODE, TT, EPS>), dim3(gxn, gyn, gzn), dim3(NTHREADS), 0, s, P, ys,
                      yo, yw, rho, kP, kF, dt, zchunk, err);
   return hipGetLastError();
 }
@@ -558,10 +597,14 @@ template <int MODE, typename TT>
 static hipError_t launch_mode(const DevParams& P, const double* ys, const double* yo, double* yw,
                               const double* rho, const double* kP, const double* kF, double dt,
                               unsigned long long* err, hipStream_t s) {
+  const bool eps = P.eps_dx > 0.0;
   switch (P.ndim) {
-    case 1: return launch_nd<1, MODE, TT>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
-    case 2: return launch_nd<2, MODE, TT>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
-    case 3: return launch_nd<3, MODE, TT>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 1: return eps ? launch_nd<1, MODE, TT, true>(P, ys, yo, yw, rho, kP, kF, dt, err, s)
+                       : launch_nd<1, MODE, TT, false>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 2: return eps ? launch_nd<2, MODE, TT, true>(P, ys, yo, yw, rho, kP, kF, dt, err, s)
+                       : launch_nd<2, MODE, TT, false>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 3: return eps ? launch_nd<3, MODE, TT, true>(P, ys, yo, yw, rho, kP, kF, dt, err, s)
+                       : launch_nd<3, MODE, TT, false>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     default: return hipErrorInvalidValue;
   }
 }

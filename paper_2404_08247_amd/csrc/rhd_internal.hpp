@@ -27,6 +27,7 @@ struct DevParams {
   double newton_rtol, outer_rtol;
   int kF_alias;       // 1: kappa_F == kappa_P
   int scheme;         // 0 PD-ARS, 1 RK2-SSP comparator
+  double eps_dx;      // hll_eps_cells * dx (0: plain HLL)
 };
 
 // Device error word layout (in the workspace): [0] smallest failing cell

@@ -43,6 +43,7 @@ class RHDParams(ctypes.Structure):
         ("scheme", ctypes.c_int32),
         ("newton_rtol", ctypes.c_double),
         ("outer_rtol", ctypes.c_double),
+        ("hll_eps_cells", ctypes.c_double),
     ]
 
 
@@ -114,6 +115,7 @@ def make_params(p: dict) -> RHDParams:
     rp.scheme = {"pdars": 0, "rk2ssp": 1}[p.get("scheme", "pdars")]
     rp.newton_rtol = float(p.get("newton_rtol", 1e-13))
     rp.outer_rtol = float(p.get("outer_rtol", 1e-13))
+    rp.hll_eps_cells = float(p.get("hll_eps_cells", 0.0))
     return rp
 
 

@@ -31,11 +31,12 @@ def test_library_exports_every_declared_symbol():
 def test_params_struct_layout_matches_header():
     from paper_2404_08247_amd import rhd
     # int32 ndim, closure; int64 n[3]; 6 doubles; int32 bc[3], v_order, precision,
-    # newton_maxit, outer_maxit, scheme; 2 doubles
-    assert ctypes.sizeof(rhd.RHDParams) == 8 + 24 + 48 + 32 + 16
+    # newton_maxit, outer_maxit, scheme; 3 doubles
+    assert ctypes.sizeof(rhd.RHDParams) == 8 + 24 + 48 + 32 + 24
     assert rhd.RHDParams.n.offset == 8
     assert rhd.RHDParams.bc.offset == 80
     assert rhd.RHDParams.newton_rtol.offset == 112
+    assert rhd.RHDParams.hll_eps_cells.offset == 128
 
 
 def _ws(p, k=0):
@@ -51,7 +52,8 @@ def test_workspace_size_and_validation():
     assert _ws(p, 4) > nb
     bad = [dict(p, chat=2.0), dict(p, chat=0.0), dict(p, dx=-1.0), dict(p, gamma=1.0),
            dict(p, v_order=3), dict(p, ndim=4), dict(p, n=(16, 12, 0)),
-           dict(p, newton_maxit=0), dict(p, a_r=0.0), dict(p, newton_rtol=0.0)]
+           dict(p, newton_maxit=0), dict(p, a_r=0.0), dict(p, newton_rtol=0.0),
+           dict(p, hll_eps_cells=-1.0), dict(p, hll_eps_cells=float("inf"))]
     for b in bad:
         assert _ws(b) == 0, b
     # reflecting axis needs >= 3 cells; axes beyond ndim must be 1
@@ -88,3 +90,22 @@ def test_create_rejects_bad_arguments_without_launching():
     assert L.rhd_last_error(h, ctypes.byref(cell), buf, 64) == -1
     L.rhd_destroy(h)
     L.rhd_destroy(None)
+
+
+def test_adjoint_rejects_what_it_does_not_differentiate():
+    """rhd_step_adjoint validates before any launch: reflecting axes, the RK2-SSP
+    comparator and the HLL eps correction are rejected with RHD_EINVAL."""
+    from paper_2404_08247_amd import rhd
+    L = rhd.lib
+    fake = ctypes.c_void_p(1 << 20)
+    base = W.config4(n=(16, 12)).params
+    for bad in (dict(base, bc=(1, 0)), dict(base, scheme="rk2ssp"), dict(base, hll_eps_cells=1.0)):
+        rp = rhd.make_params(bad)
+        nb = L.rhd_workspace_bytes(ctypes.byref(rp), 2)
+        assert nb > 0
+        h = ctypes.c_void_p()
+        assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb, 2, None, ctypes.byref(h)) == 0
+        st = L.rhd_step_adjoint(h, ctypes.c_void_p(1 << 22), ctypes.c_double(0.1), 1,
+                                ctypes.c_void_p(1 << 23), ctypes.c_void_p(1 << 24), None)
+        assert st == -1, bad
+        L.rhd_destroy(h)

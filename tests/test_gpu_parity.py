@@ -96,6 +96,33 @@ def test_transport_matches_oracle(torch_dev, orc, case):
     assert np.all(got[1 + w.ndim:] == 0.0)
 
 
+EPS_TRANSPORT_CASES = {
+    "1d_reflect_eps": lambda: W.config1(n=300, hll_eps_cells=2.0),
+    "2d_periodic_eps": lambda: W.config4(n=(70, 21), hll_eps_cells=1.0),
+    "3d_mixed_bc_eps": lambda: W.config5(n=(33, 18, 21), bc=(1, 0, 1), precision="fp64",
+                                         hll_eps_cells=3.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EPS_TRANSPORT_CASES))
+def test_transport_with_eps_correction_matches_oracle(torch_dev, orc, case):
+    torch, dev = torch_dev
+    w = EPS_TRANSPORT_CASES[case]()
+    _say("transport eps", case, w.n)
+    y = _rough_state(w, 9)
+    kF = w.kappa_P if w.kappa_F is None else w.kappa_F
+    ref = orc.transport(w.params, y, w.rho, kF)
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, y)
+    sd = torch.zeros_like(yd)
+    S.transport(yd, sd)
+    err = _rel_err(sd.cpu().numpy(), ref, range(1 + w.ndim))
+    assert err.max() < 1e-12, err
+    # the correction is active somewhere (thick faces) and changes the result
+    plain = orc.transport(dict(w.params, hll_eps_cells=0.0), y)
+    assert np.abs(plain[0] - ref[0]).max() > 1e-6 * np.abs(ref[0]).max()
+
+
 # --------------------------------------------------------------- source --
 SOURCE_CASES = {
     "c2_3d": lambda: W.config2(n=(24, 16, 12)),
@@ -157,6 +184,10 @@ STEP_CASES = {
     "c4_small_rk2ssp": (lambda: W.config4(n=(72, 40), nsteps=10, scheme="rk2ssp"), FP64_TOL),
     "c5_small_rk2ssp_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed",
                                                 scheme="rk2ssp"), MIXED_TOL),
+    "c2_small_eps": (lambda: W.config2(n=(40, 36, 20), nsteps=10, hll_eps_cells=2.0), FP64_TOL),
+    "c1_eps_rk2ssp": (lambda: W.config1(nsteps=300, scheme="rk2ssp", hll_eps_cells=1.0), FP64_TOL),
+    "c5_small_eps_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed",
+                                             hll_eps_cells=2.0), MIXED_TOL),
 }
 
 

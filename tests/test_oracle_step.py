@@ -218,3 +218,57 @@ def test_rk2ssp_equals_pdars_without_coupling(orc):
     a, _, _ = orc.step(p, y, np.ones((1, 1, 48)), zero, None, 0.3 / 48, 20)
     b, _, _ = orc.step(dict(p, scheme="rk2ssp"), y, np.ones((1, 1, 48)), zero, None, 0.3 / 48, 20)
     assert np.array_equal(a, b)
+
+
+# ------------------------------------------ Skinner-type eps (Sec. 4.2) --
+def test_eps_correction_is_plain_hll_when_optically_thin(orc):
+    # tau = hll_eps_cells dx chi <= 1 everywhere: eps = 1 and the fluxes are HLL's
+    w = W.config4(n=(20, 16))
+    p = dict(w.params, hll_eps_cells=1.0)
+    kap = np.full_like(w.kappa_P, 0.9 / (w.params["dx"] * w.rho.max()))
+    y = w.y0.copy()
+    a = orc.transport(w.params, y)
+    b = orc.transport(p, y, w.rho, kap)
+    assert np.array_equal(a, b)
+
+
+def test_eps_correction_scales_only_the_energy_dissipation(orc):
+    # With F = 0 the energy flux of HLL is pure dissipation, -S (E+ - E-)/2, so a
+    # uniform eps = 1/tau scales s_E by 1/tau exactly and leaves s_F unchanged.
+    w = W.config2(n=(12, 10, 8))
+    y = w.y0.copy()
+    y[1:4] = 0.0
+    tau = 7.5
+    p = dict(w.params, hll_eps_cells=2.0)
+    kap = np.full_like(w.kappa_P, tau / (2.0 * w.params["dx"] * w.rho))
+    a = orc.transport(w.params, y)
+    b = orc.transport(p, y, w.rho, kap)
+    np.testing.assert_allclose(b[0], a[0] / tau, rtol=1e-13, atol=1e-15 * np.abs(a[0]).max())
+    assert np.array_equal(a[1:], b[1:])
+    assert orc.face_eps(p, 3.0 / p["dx"], 3.0 / p["dx"]) == 1.0 / 6.0
+    assert orc.face_eps(w.params, 1e9, 1e9) == 1.0   # correction off
+
+
+def test_eps_correction_targets_the_hll_diffusion_not_the_rk2ssp_mode(orc):
+    # Thick diffusion pulse at n = 64 (tau_cell = 20): the HLL dissipation adds a
+    # small numerical diffusion to PD-ARS (about 2 %), which the eps correction
+    # removes; RK2-SSP keeps its C^2 dt/3 mode with or without it (the mode comes
+    # from the transport-only first stage, eq. ssp-f1, not from the Riemann solver).
+    res = {}
+    for scheme in ("pdars", "rk2ssp"):
+        for eps in (0.0, 1.0):
+            p, y, rho, kap, chi, x, Ebg = _diffusion_pulse(64)
+            p["scheme"] = scheme
+            p["hll_eps_cells"] = eps
+            D = p["chat"] / (3.0 * chi)
+            dt = 0.3 * p["dx"] / p["chat"]
+            nsteps = int(round(1.0 / dt))
+            s0 = _second_moment(x, y[0, 0, 0], Ebg)
+            yo, st, _ = orc.step(p, y, rho, kap, None, dt, nsteps)
+            assert st == 0
+            res[(scheme, eps)] = (_second_moment(x, yo[0, 0, 0], Ebg) - s0) / (2.0 * nsteps * dt) / D
+            num = p["chat"] ** 2 * dt / 6.0 / D
+    assert abs(res[("pdars", 0.0)] - 1.0) > 0.015, res
+    assert abs(res[("pdars", 1.0)] - 1.0) < 0.006, res
+    for eps in (0.0, 1.0):
+        assert abs(res[("rk2ssp", eps)] - (1.0 + num)) < 0.03 * (1.0 + num), res
