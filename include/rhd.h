@@ -71,8 +71,8 @@ typedef struct {
   double a_r;            /* radiation constant: 4 pi B / c = a_r T^4, > 0 */
   double kB_over_mu;     /* k_B / (mu m_H), > 0 */
   int32_t bc[3];         /* RHD_BC_PERIODIC or RHD_BC_REFLECT per axis (reflect needs n >= 3) */
-  int32_t v_order;       /* 1: O(v/c) source terms, eq. numF1; 2: O(v^2/c^2), eq. numF2
-                            (order 2 needs kappa_F == kappa_P: pass kappa_F = NULL or kappa_P) */
+  int32_t v_order;       /* 1: O(v/c) source terms, eq. numF1; 2: O(v^2/c^2): eq. numF2, or
+                            with kappa_F != kappa_P the 3x3 flux system of eq. fupdate-G1 */
   int32_t precision;     /* RHD_FP64, or RHD_MIXED: transport stencil in float32, state,
                             flux-divergence accumulation and the source in float64 */
   int32_t newton_maxit;  /* inner Newton iteration cap (>= 1; 50 recommended) */

@@ -475,18 +475,45 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
     const S Tn2 = Tn * Tn;
     const S Bn = ar * Tn2 * Tn2;
 
-    // ---- flux update: eq. (numF1) (order 1) or eq. (numF2) (order 2) ----
-    for (int k = 0; k < nd; ++k) {
-      S num;
-      S den;
-      if (p->v_order == 2) {
-        num = F0[k] + ch * tau * (chiP * Bn * v[k] + chiF * Enew * Dv[k]);
-        den = S(1.0) + ch * chiF * (S(1.0) + S(0.5) * beta2) * tau;
-      } else {
-        num = F0[k] + ch * tau * (chiP * Bn * v[k] + chiF * Enew * Dv[k] + (chiF - chiE) * Enew * v[k]);
-        den = S(1.0) + ch * chiF * tau;
+    // ---- flux update ----
+    // Order 1: eq. (numF1). Order 2: eq. (fupdate) with -c G_i of eq. (G1) at
+    // t+1 (E, T and D of this pass, v lagged) is linear in F^{t+1}:
+    //   [1 + chat tau chi_F (1 + beta^2/2)] F_i + chat tau (chi_F - chi_E) (2/c^2) v_i (v.F)
+    //     = F_i(t) + chat tau [chi_P a T^4 v_i + chi_F E (D v)_i + (chi_F - chi_E) E v_i],
+    // a 3x3 (nd x nd) system, solved here by Gaussian elimination with partial
+    // pivoting; for chi_F = chi_E it is diagonal and reduces to eq. (numF2).
+    if (p->v_order == 2) {
+      S Mx[3][3], bx[3];
+      const S a = S(1.0) + ch * chiF * (S(1.0) + S(0.5) * beta2) * tau;
+      const S bfac = ch * tau * (chiF - chiE) * S(2.0) / (c * c);
+      for (int i = 0; i < nd; ++i) {
+        for (int j = 0; j < nd; ++j) Mx[i][j] = (i == j ? a : S(0.0)) + bfac * v[i] * v[j];
+        bx[i] = F0[i] + ch * tau * (chiP * Bn * v[i] + chiF * Enew * Dv[i] + (chiF - chiE) * Enew * v[i]);
       }
-      Fnew[k] = num / den;
+      for (int col = 0; col < nd; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < nd; ++i)
+          if (val(sabs(Mx[i][col])) > val(sabs(Mx[piv][col]))) piv = i;
+        if (piv != col) {
+          for (int j = 0; j < nd; ++j) std::swap(Mx[col][j], Mx[piv][j]);
+          std::swap(bx[col], bx[piv]);
+        }
+        for (int i = col + 1; i < nd; ++i) {
+          const S f = Mx[i][col] / Mx[col][col];
+          for (int j = col; j < nd; ++j) Mx[i][j] = Mx[i][j] - f * Mx[col][j];
+          bx[i] = bx[i] - f * bx[col];
+        }
+      }
+      for (int i = nd - 1; i >= 0; --i) {
+        S acc = bx[i];
+        for (int j = i + 1; j < nd; ++j) acc = acc - Mx[i][j] * Fnew[j];
+        Fnew[i] = acc / Mx[i][i];
+      }
+    } else {
+      for (int k = 0; k < nd; ++k) {
+        const S num = F0[k] + ch * tau * (chiP * Bn * v[k] + chiF * Enew * Dv[k] + (chiF - chiE) * Enew * v[k]);
+        Fnew[k] = num / (S(1.0) + ch * chiF * tau);
+      }
     }
     // ---- momentum update (conserves rho v + F/(c chat)) ----
     S vnew[3];

@@ -192,7 +192,6 @@ rhd_status rhd_create(const rhd_params* p, const double* rho, const double* kapp
     return RHD_EINVAL;
   if (adjoint_segment_len < 0 || adjoint_segment_len > 1000000) return RHD_EINVAL;
   const bool alias = (kappa_F == nullptr || kappa_F == kappa_P);
-  if (p->v_order == 2 && !alias) return RHD_EINVAL;
   const Layout L = layout(p, adjoint_segment_len);
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < L.total)
     return RHD_EWORKSPACE;

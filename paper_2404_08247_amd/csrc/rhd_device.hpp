@@ -258,16 +258,21 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     closure_ig(P.closure, P.c, Eb, F2, iso, g);   // D frozen for this pass
     const double vDv = iso * v2 + g * vF * vF;
     // R/(tau chat) = A(T) - B E + C  =>  E(E_gas, R) = (A(T) + C - R/(tau chat)) / B.
-    // Order 2 (chi_F = chi_E): B = chi_E a1 with a1 = 1 + beta^2/2, and the flux
-    // update divides by a2 = 1 + chat tau chi_F a1; one reciprocal of a1 a2
-    // gives both 1/B and 1/a2.
-    double inv_B, inv_den;
+    // Order 2: B = chi_E a1 - (chi_F - chi_E)(beta^2 + v.D.v/c^2) with
+    // a1 = 1 + beta^2/2, and the flux update divides by a2 = 1 + chat tau chi_F a1.
+    // With chi_F = chi_E, B = chi_E a1 and one reciprocal of a1 a2 gives both.
+    double inv_B, inv_den, a2 = 1.0;
     if (o2) {
       const double a1 = 1.0 + 0.5 * b2;
-      const double a2 = 1.0 + ctau * chiF * a1;
-      const double q = rcp(a1 * a2);
-      inv_B = q * a2 * inv_chiE;
-      inv_den = q * a1;
+      a2 = 1.0 + ctau * chiF * a1;
+      if (chiF == chiE) {
+        const double q = rcp(a1 * a2);
+        inv_B = q * a2 * inv_chiE;
+        inv_den = q * a1;
+      } else {
+        inv_B = rcp(chiE * a1 - (chiF - chiE) * (b2 + vDv * P.inv_c2));
+        inv_den = rcp(a2);
+      }
     } else {
       inv_B = inv_chiE;
       inv_den = inv_den_o1;
@@ -298,18 +303,36 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       break;
     }
 
-    // ---- energy from conservation; flux (eq. numF1 / numF2) and momentum ----
+    // ---- energy from conservation; flux and momentum ----
+    // Order 1: eq. numF1. Order 2: eq. fupdate with eq. G1 at t+1 is
+    //   a F + b v (v.F) = rhs,  a = 1 + chat tau chi_F (1 + beta^2/2),
+    //   b = 2 chat tau (chi_F - chi_E)/c^2,
+    //   rhs = F(t) + chat tau [chi_P a T^4 v + chi_F E D v + (chi_F - chi_E) E v],
+    // solved by Sherman-Morrison: F = (rhs - b v (v.rhs)/(a + b v^2))/a (eq. numF2
+    // when chi_F = chi_E).
     Enew = E0 - P.chat_over_c * (Egas - Eg0);
     const double Tn = (Egas - KE) * inv_Cv;
     const double Tn2 = Tn * Tn;
     const double Bn = ar * Tn2 * Tn2;
-    const double xv = chiP * Bn + (o2 ? 0.0 : (chiF - chiE) * Enew);
+    const double xv = chiP * Bn + (chiF - chiE) * Enew;
     const double gvF = g * vF;
-    double v2n = 0.0, wF_new = 0.0, Fv_new = 0.0;
+    double rhs[ND];
+    double vr = 0.0;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
       const double Dvk = iso * v[k] + gvF * Fb[k];       // (D v)_k with the frozen D
-      const double Fn = (F0[k] + ctau * (xv * v[k] + chiF * Enew * Dvk)) * inv_den;
+      rhs[k] = F0[k] + ctau * (xv * v[k] + chiF * Enew * Dvk);
+      vr += v[k] * rhs[k];
+    }
+    double corr = 0.0;   // b (v.rhs)/(a + b v^2)
+    if (o2 && chiF != chiE) {
+      const double bb = 2.0 * ctau * (chiF - chiE) * P.inv_c2;
+      corr = bb * vr * rcp(a2 + bb * v2);
+    }
+    double v2n = 0.0, wF_new = 0.0, Fv_new = 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      const double Fn = (rhs[k] - corr * v[k]) * inv_den;
       const double vn = (P0[k] - (Fn - F0[k]) * P.inv_c_chat) * inv_rho;
       v2n += vn * vn;
       wF_new += vn * Fn;

@@ -47,6 +47,8 @@ CASES = {
     "c5_3d_fp64": lambda: W.config5(n=(12, 10, 8), nsteps=2, precision="fp64"),
     "c2_3d": lambda: W.config2(n=(12, 10, 8), nsteps=2),
     "c5_3d_order1": lambda: W.config5(n=(10, 8, 8), nsteps=2, precision="fp64", v_order=1),
+    "c3_3d_order2_kF": lambda: W.config3(n=(12, 10, 8), nsteps=2, precision="fp64"),
+    "c4_2d_order1_kF": lambda: W.config4(n=(20, 16), nsteps=3, v_order=1),
 }
 
 
@@ -68,21 +70,31 @@ def test_adjoint_dot_product_matches_oracle_dual(torch_dev, orc, case):
         dy[1 + d] = 1e-3 * p["c"] * y0[0] * rng.uniform(-1, 1, sh)
         dy[2 + nd + d] = 1e-3 * rng.uniform(-1, 1, sh)
     dk = w.kappa_P * rng.uniform(-1, 1, sh)
-    yN, t, st, _ = orc.step_dual(p, y0, dy, w.rho, w.kappa_P, dk, None, None, w.dt, w.nsteps)
+    kF = dkF = None
+    if case.endswith("_kF"):   # a distinct flux-mean opacity, with its own direction
+        kF = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, sh)
+        dkF = kF * rng.uniform(-1, 1, sh)
+    yN, t, st, _ = orc.step_dual(p, y0, dy, w.rho, w.kappa_P, dk, kF, dkF, w.dt, w.nsteps)
     assert st == 0
     lam = np.zeros_like(yN)
     for v in range(w.nvar):
         lam[v] = rng.normal(size=sh) / max(np.abs(yN[v]).max(), 1e-300)
     lhs = float((lam * t).sum())
 
-    S = rhd.Solver(p, _to(torch_dev, w.rho), _to(torch_dev, w.kappa_P), None, w.nsteps, dev)
+    S = rhd.Solver(p, _to(torch_dev, w.rho), _to(torch_dev, w.kappa_P),
+                   None if kF is None else _to(torch_dev, kF), w.nsteps, dev)
     lam_d = _to(torch_dev, lam)
     gk = torch.zeros_like(S.kappa_P)
-    S.step_adjoint(_to(torch_dev, y0), w.dt, w.nsteps, lam_d, gk, None)
+    gkF = None if kF is None else torch.zeros_like(S.kappa_P)
+    S.step_adjoint(_to(torch_dev, y0), w.dt, w.nsteps, lam_d, gk, gkF)
     lam0 = lam_d.cpu().numpy()
     g = gk.cpu().numpy()
     rhs = float((lam0 * dy).sum() + (g * dk).sum())
     terms = np.abs(lam0 * dy).sum() + np.abs(g * dk).sum()
+    if kF is not None:
+        gF = gkF.cpu().numpy()
+        rhs += float((gF * dkF).sum())
+        terms += np.abs(gF * dkF).sum()
     _say("  <lam, J d> =", lhs, " <J^T lam, d> =", rhs, " rel", abs(lhs - rhs) / abs(lhs))
     assert abs(lhs - rhs) <= 1e-9 * terms, (lhs, rhs, terms)
 

@@ -132,6 +132,8 @@ SOURCE_CASES = {
     "c1_1d": lambda: W.config1(n=256),
     "c5_order1_m1": lambda: W.config5(n=(20, 12, 10), precision="fp64", v_order=1),
     "c3_order1_kF": lambda: W.config3(n=(20, 12, 10), precision="fp64", v_order=1),
+    "c3_order2_kF": lambda: W.config3(n=(20, 12, 10), precision="fp64", v_order=2),
+    "c4_order2_kF": lambda: W.config4(n=(40, 24)),
 }
 
 
@@ -141,7 +143,7 @@ def test_source_matches_oracle(torch_dev, orc, case, theta):
     w = SOURCE_CASES[case]()
     _say("source", case, theta, w.n)
     y = _rough_state(w, 11, fmax=0.5)
-    if case == "c3_order1_kF":
+    if case.endswith("_kF"):
         rng = np.random.default_rng(3)
         w.kappa_F = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, w.kappa_P.shape)
     tau = theta * w.dt
@@ -171,6 +173,13 @@ def test_stage1_matches_oracle(torch_dev, orc):
 
 
 # ------------------------------------------------------- whole steps --
+def _with_kF(w, seed=4):
+    """The workload with a distinct flux-mean opacity (0.3x..3x kappa_P per cell)."""
+    rng = np.random.default_rng(seed)
+    w.kappa_F = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, w.kappa_P.shape)
+    return w
+
+
 STEP_CASES = {
     "c1_full_1000": (lambda: W.config1(), FP64_TOL),
     "c2_small": (lambda: W.config2(n=(40, 36, 20), nsteps=10), FP64_TOL),
@@ -185,6 +194,9 @@ STEP_CASES = {
     "c5_small_rk2ssp_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed",
                                                 scheme="rk2ssp"), MIXED_TOL),
     "c2_small_eps": (lambda: W.config2(n=(40, 36, 20), nsteps=10, hll_eps_cells=2.0), FP64_TOL),
+    "c3_small_order2_kF": (lambda: _with_kF(W.config3(n=(48, 24, 20), nsteps=8, precision="fp64")),
+                           FP64_TOL),
+    "c5_small_order2_kF_mixed": (lambda: _with_kF(W.config5(n=(36, 20, 18), nsteps=6)), MIXED_TOL),
     "c1_eps_rk2ssp": (lambda: W.config1(nsteps=300, scheme="rk2ssp", hll_eps_cells=1.0), FP64_TOL),
     "c5_small_eps_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed",
                                              hll_eps_cells=2.0), MIXED_TOL),

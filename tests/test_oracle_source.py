@@ -346,7 +346,9 @@ def test_source_solves_the_fully_implicit_local_system(orc, order):
         rho = np.full(ncell, 1.0)
         tau_cell = 10.0 ** rng.uniform(-3, 3, ncell)
         kP = tau_cell / (rho * (1.0 / 64))
-        kF = kP * (10.0 ** rng.uniform(-0.5, 0.5, ncell) if order == 1 else 1.0)
+        # distinct flux-mean opacity at both orders (order 2 then needs the 3x3
+        # flux solve; order 1 is eq. numF1)
+        kF = kP * 10.0 ** rng.uniform(-0.5, 0.5, ncell)
         y = np.zeros((8, 1, 1, ncell))
         Tg = rng.uniform(0.5, 2.0, ncell)
         Tr = rng.uniform(0.5, 2.0, ncell)
