@@ -150,6 +150,21 @@ rhd_status rhd_step_timed(rhd_handle* h, double* state, double dt, int32_t nstep
  * out is a HOST array of 1 + ndim doubles. */
 rhd_status rhd_conserved_totals(rhd_handle* h, const double* state, double* out);
 
+/* Optional fields of the local source (Sec. 3.3), bound to the handle until
+ * replaced (the caller keeps them alive); both take effect from the next call.
+ * rhd_set_energy_opacity: energy-mean opacity per unit mass kappa_E (device float64
+ *   [nz][ny][nx], chi_E = rho kappa_E in eq. G0-G1 and in the Jacobian of the inner
+ *   Newton); NULL (or kappa_P) restores kappa_E = kappa_P. rhd_step_adjoint holds a
+ *   separate kappa_E fixed (no gradient with respect to it).
+ * rhd_set_radiation_source: radiation injection rate j per unit volume (device
+ *   float64 [nz][ny][nx]); every implicit stage adds S = j theta dt to the radiation
+ *   energy (the optional S of eq. FGFR: F_R = E - E(t) - (R + S), E recovered as
+ *   E(t) - (chat/c)(E_gas - E_gas(t)) + S); NULL removes it. The source terms' partial
+ *   derivatives do not depend on S, so the adjoint covers it.
+ * Both return RHD_EINVAL for a misaligned pointer. */
+rhd_status rhd_set_energy_opacity(rhd_handle* h, const double* kappa_E);
+rhd_status rhd_set_radiation_source(rhd_handle* h, const double* j);
+
 /* Error details of the last call on h: *cell = smallest failing cell index (or
  * -1), msg receives a NUL-terminated description (truncated to len). Returns the
  * status of the last call. */

@@ -62,13 +62,13 @@ def lib():
         pp = ctypes.POINTER(OracleParams)
         i64p = ctypes.POINTER(ctypes.c_int64)
         ip = ctypes.POINTER(ctypes.c_int)
-        L.oracle_step.argtypes = [pp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, i64p]
+        L.oracle_step.argtypes = [pp, dp, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, i64p]
         L.oracle_step.restype = ctypes.c_int
-        L.oracle_stage1.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_double, i64p]
+        L.oracle_stage1.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double, i64p]
         L.oracle_stage1.restype = ctypes.c_int
         L.oracle_transport.argtypes = [pp, dp, dp, dp, dp]
         L.oracle_transport.restype = None
-        L.oracle_source.argtypes = [pp, dp, dp, dp, dp, ctypes.c_double, ip, ip, i64p]
+        L.oracle_source.argtypes = [pp, dp, dp, dp, dp, dp, dp, ctypes.c_double, ip, ip, i64p]
         L.oracle_source.restype = ctypes.c_int
         L.oracle_ppm_edges.argtypes = [dp, ctypes.c_int64, dp, dp]
         L.oracle_ppm_edges.restype = None
@@ -78,7 +78,7 @@ def lib():
         L.oracle_hll.restype = None
         L.oracle_face_eps.argtypes = [pp, ctypes.c_double, ctypes.c_double]
         L.oracle_face_eps.restype = ctypes.c_double
-        L.oracle_step_dual.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double,
+        L.oracle_step_dual.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double,
                                        ctypes.c_int, i64p]
         L.oracle_step_dual.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
@@ -126,23 +126,25 @@ def _c(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
-def step(p: dict, y: np.ndarray, rho, kP, kF, dt: float, nsteps: int):
-    """Run nsteps PD-ARS steps. Returns (y_new, status, fail_cell)."""
+def step(p: dict, y: np.ndarray, rho, kP, kF, dt: float, nsteps: int, kE=None, jS=None):
+    """Run nsteps steps. kE: energy-mean opacity (None: kP); jS: radiation
+    injection rate per unit volume (None: no source). Returns (y_new, status,
+    fail_cell)."""
     y = np.array(y, dtype=np.float64, order="C", copy=True)
-    rho, kP, kF = _c(rho), _c(kP), _c(kF)
+    rho, kP, kF, kE, jS = _c(rho), _c(kP), _c(kF), _c(kE), _c(jS)
     fc = ctypes.c_int64(-1)
     st = lib().oracle_step(ctypes.byref(make_params(p)), _dp(y), _dp(rho), _dp(kP), _dp(kF),
-                           float(dt), int(nsteps), ctypes.byref(fc))
+                           _dp(kE), _dp(jS), float(dt), int(nsteps), ctypes.byref(fc))
     return y, st, fc.value
 
 
-def stage1(p: dict, y: np.ndarray, rho, kP, kF, dt: float):
+def stage1(p: dict, y: np.ndarray, rho, kP, kF, dt: float, kE=None, jS=None):
     y = _c(y)
     yh = np.empty_like(y)
-    rho, kP, kF = _c(rho), _c(kP), _c(kF)
+    rho, kP, kF, kE, jS = _c(rho), _c(kP), _c(kF), _c(kE), _c(jS)
     fc = ctypes.c_int64(-1)
     st = lib().oracle_stage1(ctypes.byref(make_params(p)), _dp(y), _dp(yh), _dp(rho), _dp(kP),
-                             _dp(kF), float(dt), ctypes.byref(fc))
+                             _dp(kF), _dp(kE), _dp(jS), float(dt), ctypes.byref(fc))
     return yh, st, fc.value
 
 
@@ -157,19 +159,20 @@ def transport(p: dict, y: np.ndarray, rho=None, kF=None) -> np.ndarray:
     return s
 
 
-def source(p: dict, y: np.ndarray, rho, kP, kF, tau: float):
-    """Apply the local implicit source with theta*dt = tau to every cell.
-    Returns (y_new, status, fail_cell, newton_iters, outer_iters)."""
+def source(p: dict, y: np.ndarray, rho, kP, kF, tau: float, kE=None, jS=None):
+    """Apply the local implicit source with theta*dt = tau to every cell (kE,
+    jS as in step()). Returns (y_new, status, fail_cell, newton_iters,
+    outer_iters)."""
     y = np.array(y, dtype=np.float64, order="C", copy=True)
-    rho, kP, kF = _c(rho), _c(kP), _c(kF)
+    rho, kP, kF, kE, jS = _c(rho), _c(kP), _c(kF), _c(kE), _c(jS)
     N = rho.size
     it = np.zeros(N, dtype=np.int32)
     ou = np.zeros(N, dtype=np.int32)
     fc = ctypes.c_int64(-1)
     ip = ctypes.POINTER(ctypes.c_int)
     st = lib().oracle_source(ctypes.byref(make_params(p)), _dp(y), _dp(rho), _dp(kP), _dp(kF),
-                             float(tau), it.ctypes.data_as(ip), ou.ctypes.data_as(ip),
-                             ctypes.byref(fc))
+                             _dp(kE), _dp(jS), float(tau), it.ctypes.data_as(ip),
+                             ou.ctypes.data_as(ip), ctypes.byref(fc))
     return y, st, fc.value, it.reshape(rho.shape), ou.reshape(rho.shape)
 
 
@@ -201,15 +204,16 @@ def hll(p: dict, ndim: int, d: int, Um, Up) -> np.ndarray:
     return out
 
 
-def step_dual(p: dict, y, ty, rho, kP, tkP, kF, tkF, dt: float, nsteps: int):
-    """Forward-mode tangent of nsteps steps. Returns (y, ty, status, fail_cell)."""
+def step_dual(p: dict, y, ty, rho, kP, tkP, kF, tkF, dt: float, nsteps: int, kE=None, jS=None):
+    """Forward-mode tangent of nsteps steps (kE, jS without tangents). Returns (y,
+    ty, status, fail_cell)."""
     y = np.array(y, dtype=np.float64, order="C", copy=True)
     ty = np.array(ty, dtype=np.float64, order="C", copy=True)
-    rho, kP, tkP, kF, tkF = _c(rho), _c(kP), _c(tkP), _c(kF), _c(tkF)
+    rho, kP, tkP, kF, tkF, kE, jS = _c(rho), _c(kP), _c(tkP), _c(kF), _c(tkF), _c(kE), _c(jS)
     fc = ctypes.c_int64(-1)
     st = lib().oracle_step_dual(ctypes.byref(make_params(p)), _dp(y), _dp(ty), _dp(rho), _dp(kP),
-                                _dp(tkP), _dp(kF), _dp(tkF), float(dt), int(nsteps),
-                                ctypes.byref(fc))
+                                _dp(tkP), _dp(kF), _dp(tkF), _dp(kE), _dp(jS), float(dt),
+                                int(nsteps), ctypes.byref(fc))
     return y, ty, st, fc.value
 
 

@@ -359,16 +359,21 @@ template <> struct Tangent<Dual> {
   }
 };
 
+// kE: energy-mean opacity (chi_E = rho kE; the caller passes kP when it is not a
+// separate field). Ssrc: the optional radiation source S of eq. (FGFR) over this
+// implicit sub-step (S = j tau for an injection rate j; 0 when absent).
 template <class S>
 static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, S rho, S kP,
-                       S kF, double tau_d, int* iters_out, int* outer_out) {
+                       S kF, S kE, S Ssrc, double tau_d, int* iters_out, int* outer_out) {
   const S c = S(p->c), ch = S(p->chat);
   const S tau = S(tau_d);
   const S chiP = rho * kP;   // Planck mean (comoving)
-  const S chiE = chiP;       // energy mean taken equal to the Planck mean (grey)
+  const S chiE = rho * kE;   // energy mean
   const S chiF = rho * kF;   // flux mean
   int iters = 0, outer = 0;
-  if (val(chiP) == 0.0 && val(chiF) == 0.0) {  // no coupling: Src is the identity
+  if (val(chiP) == 0.0 && val(chiE) == 0.0 && val(chiF) == 0.0) {
+    // no coupling: R = 0, and the radiation only receives the source S
+    E = E + Ssrc;
     if (iters_out) *iters_out = 0;
     if (outer_out) *outer_out = 0;
     return ORC_OK;
@@ -389,9 +394,9 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
   S Ebar = E0;
   S Egas = Eg0;
   S R = S(0.0);
-  // E_tot: total energy in gas units, radiation weighted by c/chat (the weight
-  // of R in F_G and of the conserved sum E_gas + (c/chat) E).
-  const S Etot = Eg0 + c_over_ch * E0;
+  // E_tot: total energy in gas units, radiation (with S) weighted by c/chat (the
+  // weight of R in F_G and of the conserved sum E_gas + (c/chat) E).
+  const S Etot = Eg0 + c_over_ch * (E0 + Ssrc);
 
   S Enew = E0, Fnew[3], Pnew[3];
   for (int k = 0; k < nd; ++k) { Fnew[k] = F0[k]; Pnew[k] = P0[k]; }
@@ -437,7 +442,7 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
       S A = chiP * ar * (T2 * T2) * Afac;
       S Er = (A + Cc - R / (tau * ch)) / B;
       S FG = Egas - Eg0 + c_over_ch * R;
-      S FR = Er - E0 - R;
+      S FR = Er - E0 - (R + Ssrc);
       if (!vconv) {
         if (sabs(FG) < S(eps) * Etot && c_over_ch * sabs(FR) < S(eps) * Etot) {
           vconv = true;
@@ -470,7 +475,7 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
     // eq. (egupdate)-(eupdate) give E - E(t) = -(chat/c)(E_gas - E_gas(t)), the
     // form that keeps E_gas + (c/chat) E exact (the printed recovery formula
     // writes the inverse ratio; the two agree for chat = c).
-    Enew = E0 - (ch / c) * (Egas - Eg0);
+    Enew = E0 - (ch / c) * (Egas - Eg0) + Ssrc;
     const S Tn = (Egas - KE) / Cv;
     const S Tn2 = Tn * Tn;
     const S Bn = ar * Tn2 * Tn2;
@@ -545,10 +550,10 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
     const S Wold = Wterm(v, Fbar, Enew, Tn);
     const S Wnew = Wterm(vnew, Fnew, Enew, (Egas - KEn) / Cv);
 
-    // next pass starts from the updated v, F, E; warm start R = E - E(t)
+    // next pass starts from the updated v, F, E; warm start R = E - E(t) - S
     for (int k = 0; k < nd; ++k) { v[k] = vnew[k]; Fbar[k] = Fnew[k]; }
     Ebar = Enew;
-    R = Enew - E0;
+    R = Enew - E0 - Ssrc;
 
     S dW = sabs(Wnew - Wold);
     bool oconv = (dW <= S(p->outer_rtol) * sabs(Wold)) || (dW <= S(p->outer_rtol) * sabs(R));
@@ -579,8 +584,8 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
 
 template <class S>
 static void apply_source(const oracle_params* p, const Grid& g, S* y, const S* rho, const S* kP,
-                         const S* kF, double tau, int* status, int64_t* fail_cell, int* iters,
-                         int* outers) {
+                         const S* kF, const S* kE, const S* jS, double tau, int* status,
+                         int64_t* fail_cell, int* iters, int* outers) {
   const int nd = g.ndim;
   int st_all = ORC_OK;
   int64_t fail = -1;
@@ -598,7 +603,8 @@ static void apply_source(const oracle_params* p, const Grid& g, S* y, const S* r
         P[k] = y[(int64_t)g.vP(k) * g.N + c];
       }
       int it = 0, ou = 0;
-      int st = source_cell(p, nd, E, F, Eg, P, rho[c], kP[c], kF ? kF[c] : kP[c], tau, &it, &ou);
+      int st = source_cell(p, nd, E, F, Eg, P, rho[c], kP[c], kF ? kF[c] : kP[c],
+                           kE ? kE[c] : kP[c], jS ? jS[c] * S(tau) : S(0.0), tau, &it, &ou);
       if (iters) iters[c] = it;
       if (outers) outers[c] = ou;
       y[(int64_t)g.vE() * g.N + c] = E;
@@ -629,8 +635,8 @@ static void apply_source(const oracle_params* p, const Grid& g, S* y, const S* r
 // y(t) = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2}); y^{n+1} = Src(y(t), dt).
 template <class S>
 static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho, const S* kP,
-                       const S* kF, double dt, std::vector<S>& yh, std::vector<S>& s, int* status,
-                       int64_t* fail_cell) {
+                       const S* kF, const S* kE, const S* jS, double dt, std::vector<S>& yh,
+                       std::vector<S>& s, int* status, int64_t* fail_cell) {
   const int64_t M = (int64_t)g.nvar * g.N;
   const int nr = 1 + g.ndim;
   const S* kFx = kF ? kF : kP;   // flux-mean opacity for the optional eps correction
@@ -639,7 +645,8 @@ static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho
   for (int64_t q = 0; q < M; ++q) yh[q] = y[q];
   for (int r = 0; r < nr; ++r)
     for (int64_t c = 0; c < g.N; ++c) yh[(int64_t)r * g.N + c] = y[(int64_t)r * g.N + c] + S(dt) * s[(int64_t)r * g.N + c];
-  if (p->scheme == 0) apply_source(p, g, yh.data(), rho, kP, kF, dt, status, fail_cell, nullptr, nullptr);
+  if (p->scheme == 0)
+    apply_source(p, g, yh.data(), rho, kP, kF, kE, jS, dt, status, fail_cell, nullptr, nullptr);
   // stage 2: y(t) = (y^n + y^{n+1/2})/2 + dt/2 s(y^{n+1/2}); y^{n+1} = Src(y(t), theta = 1/2)
   transport(p, g, yh.data(), s.data(), rho, kFx);
   for (int64_t q = 0; q < M; ++q) {
@@ -648,8 +655,8 @@ static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho
     if (r < nr) comb = comb + S(0.5 * dt) * s[q];
     y[q] = comb;
   }
-  apply_source(p, g, y, rho, kP, kF, p->scheme == 0 ? 0.5 * dt : dt, status, fail_cell, nullptr,
-               nullptr);
+  apply_source(p, g, y, rho, kP, kF, kE, jS, p->scheme == 0 ? 0.5 * dt : dt, status, fail_cell,
+               nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,20 +682,25 @@ void oracle_set_threads(int n) {
 
 // y: [nvar][N] in/out. kF may be NULL (aliases kP). Returns status of the
 // first failing cell (smallest index) or 0; *fail_cell = that index or -1.
+// kE (energy-mean opacity) may be NULL (aliases kP); jS (radiation injection
+// rate per unit volume, the source S = jS theta dt of each implicit stage) may be
+// NULL (no source).
 int oracle_step(const oracle_params* p, double* y, const double* rho, const double* kP,
-                const double* kF, double dt, int nsteps, int64_t* fail_cell) {
+                const double* kF, const double* kE, const double* jS, double dt, int nsteps,
+                int64_t* fail_cell) {
   Grid g(p);
   std::vector<double> yh((size_t)g.nvar * g.N), s((size_t)g.nvar * g.N);
   int status = ORC_OK;
   int64_t fc = -1;
-  for (int n = 0; n < nsteps; ++n) pdars_step(p, g, y, rho, kP, kF, dt, yh, s, &status, &fc);
+  for (int n = 0; n < nsteps; ++n) pdars_step(p, g, y, rho, kP, kF, kE, jS, dt, yh, s, &status, &fc);
   if (fail_cell) *fail_cell = fc;
   return status;
 }
 
 // Stage 1 only (for unit parity of one stage): y_half = Src(y + dt s(y), 1).
 int oracle_stage1(const oracle_params* p, const double* y, double* yh, const double* rho,
-                  const double* kP, const double* kF, double dt, int64_t* fail_cell) {
+                  const double* kP, const double* kF, const double* kE, const double* jS,
+                  double dt, int64_t* fail_cell) {
   Grid g(p);
   const int64_t M = (int64_t)g.nvar * g.N;
   std::vector<double> s((size_t)M);
@@ -697,7 +709,7 @@ int oracle_stage1(const oracle_params* p, const double* y, double* yh, const dou
   for (int64_t q = 0; q < M; ++q) yh[q] = y[q] + ((q / g.N) < nr ? dt * s[q] : 0.0);
   int status = ORC_OK;
   int64_t fc = -1;
-  apply_source(p, g, yh, rho, kP, kF, dt, &status, &fc, nullptr, nullptr);
+  apply_source(p, g, yh, rho, kP, kF, kE, jS, dt, &status, &fc, nullptr, nullptr);
   if (fail_cell) *fail_cell = fc;
   return status;
 }
@@ -712,11 +724,12 @@ void oracle_transport(const oracle_params* p, const double* y, double* s, const 
 
 // Src applied to every cell with theta*dt = tau. iters/outers may be NULL.
 int oracle_source(const oracle_params* p, double* y, const double* rho, const double* kP,
-                  const double* kF, double tau, int* iters, int* outers, int64_t* fail_cell) {
+                  const double* kF, const double* kE, const double* jS, double tau, int* iters,
+                  int* outers, int64_t* fail_cell) {
   Grid g(p);
   int status = ORC_OK;
   int64_t fc = -1;
-  apply_source(p, g, y, rho, kP, kF, tau, &status, &fc, iters, outers);
+  apply_source(p, g, y, rho, kP, kF, kE, jS, tau, &status, &fc, iters, outers);
   if (fail_cell) *fail_cell = fc;
   return status;
 }
@@ -747,22 +760,28 @@ double oracle_face_eps(const oracle_params* p, double chi_a, double chi_b) {
 
 // Dual-number step: (y, ty) value and tangent; tangents of rho are zero;
 // (kP, tkP), (kF, tkF) opacities with tangents (kF == NULL aliases kP and tkP).
+// kE (NULL: kP, with kP's tangent) and jS (NULL: none) enter without tangents.
 int oracle_step_dual(const oracle_params* p, double* y, double* ty, const double* rho,
                      const double* kP, const double* tkP, const double* kF, const double* tkF,
-                     double dt, int nsteps, int64_t* fail_cell) {
+                     const double* kE, const double* jS, double dt, int nsteps,
+                     int64_t* fail_cell) {
   Grid g(p);
   const int64_t M = (int64_t)g.nvar * g.N;
   std::vector<Dual> Y((size_t)M), yh((size_t)M), s((size_t)M), R((size_t)g.N), KP((size_t)g.N),
-      KF((size_t)g.N);
+      KF((size_t)g.N), KE((size_t)g.N), JS((size_t)g.N);
   for (int64_t q = 0; q < M; ++q) Y[q] = Dual(y[q], ty[q]);
   for (int64_t c = 0; c < g.N; ++c) {
     R[c] = Dual(rho[c], 0.0);
     KP[c] = Dual(kP[c], tkP ? tkP[c] : 0.0);
     KF[c] = kF ? Dual(kF[c], tkF ? tkF[c] : 0.0) : KP[c];
+    KE[c] = kE ? Dual(kE[c], 0.0) : KP[c];
+    JS[c] = Dual(jS ? jS[c] : 0.0, 0.0);
   }
   int status = ORC_OK;
   int64_t fc = -1;
-  for (int n = 0; n < nsteps; ++n) pdars_step(p, g, Y.data(), R.data(), KP.data(), KF.data(), dt, yh, s, &status, &fc);
+  for (int n = 0; n < nsteps; ++n)
+    pdars_step(p, g, Y.data(), R.data(), KP.data(), KF.data(), KE.data(), jS ? JS.data() : nullptr,
+               dt, yh, s, &status, &fc);
   for (int64_t q = 0; q < M; ++q) { y[q] = Y[q].v; ty[q] = Y[q].d; }
   if (fail_cell) *fail_cell = fc;
   return status;

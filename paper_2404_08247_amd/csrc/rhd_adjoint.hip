@@ -247,9 +247,9 @@ __device__ void hll_flux_s(const DevParams& P, const S* Um, const S* Up, S* fl) 
 //   f_E = (chat/c) g_0, f_Egas = -g_0, f_F_k = c chat g_k, f_p_k = -g_k
 // (eq. egupdate-fupdate in RSLA form).
 template <int ND, typename S>
-__device__ void source_g(const DevParams& P, const S* z, S rho, S kP, S kF, S* gout) {
+__device__ void source_g(const DevParams& P, const S* z, S rho, S kP, S kF, S kE, S* gout) {
   const double c = P.c;
-  const S chiP = rho * kP, chiE = chiP, chiF = rho * kF;
+  const S chiP = rho * kP, chiE = rho * kE, chiF = rho * kF;
   const S E = z[0], Eg = z[1 + ND];
   S v[ND];
   S v2 = mk0<S>(0.0), vF = mk0<S>(0.0), F2 = mk0<S>(0.0);
@@ -329,7 +329,11 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
     }
   };
   const double rq = rho[q], kp = kP[q], kf = P.kF_alias ? kp : kF[q];
-  if (rq * kp == 0.0 && rq * kf == 0.0) {   // source is the identity there: mu = lam
+  // energy-mean opacity: a separate field (held fixed: no gradient), or kappa_P
+  // (then its tangent is kappa_P's: eP = 1)
+  const double ke = P.kE ? P.kE[q] : kp;
+  const double eP = P.kE ? 0.0 : 1.0;
+  if (rq * kp == 0.0 && rq * kf == 0.0 && rq * ke == 0.0) {   // Src is E += S there: mu = lam
     outputs(lv);
     return;
   }
@@ -347,7 +351,7 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
     Dd zd[M], gd[m];
 #pragma unroll
     for (int i = 0; i < M; ++i) zd[i] = mk(z[i], i == j ? 1.0 : 0.0);
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), gd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), mk(ke), gd);
 #pragma unroll
     for (int i = 0; i < m; ++i) G[i][j] = gd[i].d;
   }
@@ -449,25 +453,25 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
 #pragma unroll
   for (int i = 0; i < M; ++i) zd[i] = mk(z[i]);
   if (P.kF_alias) {
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kp, gkF ? 0.0 : 1.0), gd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kp, gkF ? 0.0 : 1.0), mk(ke, eP), gd);
     double g = 0.0;
 #pragma unroll
     for (int i = 0; i < m; ++i) g += gd[i].d * um[i];
     gkP[q] += tau * g;
     if (gkF) {
-      source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kp, 1.0), gd);
+      source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kp, 1.0), mk(ke), gd);
       double h = 0.0;
 #pragma unroll
       for (int i = 0; i < m; ++i) h += gd[i].d * um[i];
       gkF[q] += tau * h;
     }
   } else {
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kf), gd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kf), mk(ke, eP), gd);
     double g = 0.0;
 #pragma unroll
     for (int i = 0; i < m; ++i) g += gd[i].d * um[i];
     gkP[q] += tau * g;
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf, 1.0), gd);
+    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf, 1.0), mk(ke), gd);
     double h = 0.0;
 #pragma unroll
     for (int i = 0; i < m; ++i) h += gd[i].d * um[i];

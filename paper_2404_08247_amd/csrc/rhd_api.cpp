@@ -384,6 +384,20 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
   return finish(h);
 }
 
+rhd_status rhd_set_energy_opacity(rhd_handle* h, const double* kappa_E) {
+  if (!h) return RHD_EINVAL;
+  if (misaligned(kappa_E)) return set_err(h, RHD_EINVAL, -1, "misaligned kappa_E");
+  h->dp.kE = (kappa_E == h->kP) ? nullptr : kappa_E;
+  return set_err(h, RHD_OK, -1, "");
+}
+
+rhd_status rhd_set_radiation_source(rhd_handle* h, const double* j) {
+  if (!h) return RHD_EINVAL;
+  if (misaligned(j)) return set_err(h, RHD_EINVAL, -1, "misaligned radiation source");
+  h->dp.jS = j;
+  return set_err(h, RHD_OK, -1, "");
+}
+
 rhd_status rhd_last_error(const rhd_handle* h, int64_t* cell, char* msg, size_t len) {
   if (!h) return RHD_EINVAL;
   if (cell) *cell = h->last_cell;

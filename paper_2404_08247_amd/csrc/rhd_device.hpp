@@ -201,14 +201,20 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
   }
 }
 
-// inv_tch = 1/(tau chat) is passed in (uniform over a launch).
+// inv_tch = 1/(tau chat) is passed in (uniform over a launch). kE: energy-mean
+// opacity (kP when it is not a separate field); Ssrc: the radiation source S of
+// eq. FGFR over this sub-step (0 when absent).
 template <int ND>
 __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double& Eg, double* Pm,
-                                double rho, double kP, double kF, double tau, double inv_tch) {
+                                double rho, double kP, double kF, double kE, double Ssrc,
+                                double tau, double inv_tch) {
   const double chiP = rho * kP;
-  const double chiE = chiP;
+  const double chiE = rho * kE;
   const double chiF = rho * kF;
-  if (chiP == 0.0 && chiF == 0.0) return 0u;
+  if (chiP == 0.0 && chiE == 0.0 && chiF == 0.0) {   // no coupling: E += S only
+    E += Ssrc;
+    return 0u;
+  }
   const double ch = P.chat;
   const double k_cc = P.c_over_chat;
   const double Cv = rho * P.cv_mass;
@@ -233,11 +239,11 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   double Eb = E0;
   double Egas = Eg0;
   double R = 0.0;
-  const double tol = P.newton_rtol * (Eg0 + k_cc * E0);
+  const double tol = P.newton_rtol * (Eg0 + k_cc * (E0 + Ssrc));
   // simplified Jacobian (fixed for the call): dF_R/dR and the T^3 factor of
-  // dF_R/dE_gas (chi_P / chi_E = 1 for the grey opacities used here)
+  // dF_R/dE_gas = (1/C_v) d/dT (chi_P/chi_E a T^4)
   const double J22 = -inv_tch * inv_chiE - 1.0;
-  const double J21c = 4.0 * ar * inv_Cv;
+  const double J21c = 4.0 * ar * inv_Cv * (kP == kE ? 1.0 : chiP * inv_chiE);
   const double ctau = ch * tau;
   // order 1: 1/B = 1/chi_E and the flux denominator do not change between passes
   const double inv_den_o1 = o2 ? 0.0 : rcp(1.0 + ctau * chiF);
@@ -287,7 +293,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       const double T2 = T * T;
       const double Er = (Aco * T2 * T2 + Cc - R * inv_tch) * inv_B;
       const double FG = Egas - Eg0 + k_cc * R;
-      const double FR = Er - E0 - R;
+      const double FR = Er - E0 - (R + Ssrc);
       if (fabs(FG) < tol && k_cc * fabs(FR) < tol) {
         conv = true;
         break;
@@ -310,7 +316,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     //   rhs = F(t) + chat tau [chi_P a T^4 v + chi_F E D v + (chi_F - chi_E) E v],
     // solved by Sherman-Morrison: F = (rhs - b v (v.rhs)/(a + b v^2))/a (eq. numF2
     // when chi_F = chi_E).
-    Enew = E0 - P.chat_over_c * (Egas - Eg0);
+    Enew = E0 - P.chat_over_c * (Egas - Eg0) + Ssrc;
     const double Tn = (Egas - KE) * inv_Cv;
     const double Tn2 = Tn * Tn;
     const double Bn = ar * Tn2 * Tn2;
@@ -361,7 +367,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       Fb[k] = F[k];
     }
     Eb = Enew;
-    R = Enew - E0;
+    R = Enew - E0 - Ssrc;
     const double dW = fabs(W_new - W_old);
     if (dW <= P.outer_rtol * fabs(W_old) || dW <= P.outer_rtol * fabs(R)) break;
   }

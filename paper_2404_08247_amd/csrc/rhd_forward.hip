@@ -256,7 +256,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     // stage 2 the whole own-cell y^n; rho and kappa.
     constexpr int NPRE = (MODE == MODE_STAGE2) ? (1 + ND) + (2 + 2 * ND) : (1 + ND);
     double pre[NPRE];
-    double pre_rho = 1.0, pre_kp = 0.0, pre_kf = 0.0;
+    double pre_rho = 1.0, pre_kp = 0.0, pre_kf = 0.0, pre_ke = 0.0, pre_j = 0.0;
     if constexpr (MODE != MODE_TRANSPORT) {
       const long long qc = k * plane + colq;   // in range for every thread
 #pragma unroll
@@ -268,6 +268,8 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       pre_rho = rho[qc];
       pre_kp = kP[qc];
       pre_kf = P.kF_alias ? pre_kp : kF[qc];
+      pre_ke = P.kE ? P.kE[qc] : pre_kp;
+      if (P.jS) pre_j = P.jS[qc];
     }
     // ---------------- stage the plane's (E, F) tile in LDS ----------------
     double own[NR];
@@ -490,8 +492,8 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       // of the step with the full dt
       const unsigned st = (MODE == MODE_STAGE1 && P.scheme == 1)
                               ? 0u
-                              : source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, tau_src,
-                                                inv_tch);
+                              : source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, pre_ke,
+                                                pre_j * tau_src, tau_src, inv_tch);
       if (st) report(err, q, st);
       yw[q] = E;
 #pragma unroll
@@ -518,7 +520,8 @@ k_source(DevParams P, double* y, const double* __restrict__ rho, const double* _
     Pm[k] = y[(2 + ND + k) * N + q];
   }
   const double kp = kP[q];
-  const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q], tau,
+  const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q],
+                                     P.kE ? P.kE[q] : kp, P.jS ? P.jS[q] * tau : 0.0, tau,
                                      rcp(tau * P.chat));
   if (st) report(err, q, st);
   y[q] = E;

@@ -28,6 +28,8 @@ struct DevParams {
   int kF_alias;       // 1: kappa_F == kappa_P
   int scheme;         // 0 PD-ARS, 1 RK2-SSP comparator
   double eps_dx;      // hll_eps_cells * dx (0: plain HLL)
+  const double* kE;   // energy-mean opacity per unit mass (device), or null: kappa_P
+  const double* jS;   // radiation injection rate per unit volume (device), or null: none
 };
 
 // Device error word layout (in the workspace): [0] smallest failing cell

@@ -21,7 +21,7 @@ _STATUS = {0: "RHD_OK", -1: "RHD_EINVAL", -2: "RHD_ENEWTON", -3: "RHD_ENONPHYS",
            -5: "RHD_EWORKSPACE"}
 EXPORTED = ["rhd_workspace_bytes", "rhd_create", "rhd_step", "rhd_step_adjoint", "rhd_transport",
             "rhd_source", "rhd_stage1", "rhd_step_timed", "rhd_conserved_totals", "rhd_last_error",
-            "rhd_destroy"]
+            "rhd_destroy", "rhd_set_energy_opacity", "rhd_set_radiation_source"]
 
 
 class RHDParams(ctypes.Structure):
@@ -86,6 +86,10 @@ def _load():
     L.rhd_last_error.restype = ctypes.c_int
     L.rhd_destroy.argtypes = [vp]
     L.rhd_destroy.restype = None
+    L.rhd_set_energy_opacity.argtypes = [vp, vp]
+    L.rhd_set_energy_opacity.restype = ctypes.c_int
+    L.rhd_set_radiation_source.argtypes = [vp, vp]
+    L.rhd_set_radiation_source.restype = ctypes.c_int
     return L
 
 
@@ -202,6 +206,16 @@ class Solver:
 
     def source(self, y: torch.Tensor, tau: float, raise_on_error=True) -> int:
         return self._check(lib.rhd_source(self._h, self._state(y), float(tau)), raise_on_error)
+
+    def set_kappa_E(self, kappa_E: Optional[torch.Tensor]) -> int:
+        """Energy-mean opacity field (None: kappa_E = kappa_P); kept referenced."""
+        self.kappa_E = kappa_E
+        return self._check(lib.rhd_set_energy_opacity(self._h, _ptr(kappa_E)))
+
+    def set_radiation_source(self, j: Optional[torch.Tensor]) -> int:
+        """Radiation injection rate per unit volume (None: no source); kept referenced."""
+        self.j_source = j
+        return self._check(lib.rhd_set_radiation_source(self._h, _ptr(j)))
 
     def conserved_totals(self, y: torch.Tensor):
         out = (ctypes.c_double * (1 + self.ndim))()

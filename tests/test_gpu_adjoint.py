@@ -49,6 +49,7 @@ CASES = {
     "c5_3d_order1": lambda: W.config5(n=(10, 8, 8), nsteps=2, precision="fp64", v_order=1),
     "c3_3d_order2_kF": lambda: W.config3(n=(12, 10, 8), nsteps=2, precision="fp64"),
     "c4_2d_order1_kF": lambda: W.config4(n=(20, 16), nsteps=3, v_order=1),
+    "c2_3d_kE_src": lambda: W.config2(n=(12, 10, 8), nsteps=2),
 }
 
 
@@ -74,7 +75,12 @@ def test_adjoint_dot_product_matches_oracle_dual(torch_dev, orc, case):
     if case.endswith("_kF"):   # a distinct flux-mean opacity, with its own direction
         kF = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, sh)
         dkF = kF * rng.uniform(-1, 1, sh)
-    yN, t, st, _ = orc.step_dual(p, y0, dy, w.rho, w.kappa_P, dk, kF, dkF, w.dt, w.nsteps)
+    kE = jS = None
+    if case.endswith("_kE_src"):   # a separate energy-mean opacity (held fixed) and a source
+        kE = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, sh)
+        jS = rng.uniform(0.0, 0.5, sh) * y0[0] / (w.nsteps * w.dt)
+    yN, t, st, _ = orc.step_dual(p, y0, dy, w.rho, w.kappa_P, dk, kF, dkF, w.dt, w.nsteps,
+                                 kE=kE, jS=jS)
     assert st == 0
     lam = np.zeros_like(yN)
     for v in range(w.nvar):
@@ -83,6 +89,9 @@ def test_adjoint_dot_product_matches_oracle_dual(torch_dev, orc, case):
 
     S = rhd.Solver(p, _to(torch_dev, w.rho), _to(torch_dev, w.kappa_P),
                    None if kF is None else _to(torch_dev, kF), w.nsteps, dev)
+    if kE is not None:
+        S.set_kappa_E(_to(torch_dev, kE))
+        S.set_radiation_source(_to(torch_dev, jS))
     lam_d = _to(torch_dev, lam)
     gk = torch.zeros_like(S.kappa_P)
     gkF = None if kF is None else torch.zeros_like(S.kappa_P)

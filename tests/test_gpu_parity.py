@@ -157,6 +157,30 @@ def test_source_matches_oracle(torch_dev, orc, case, theta):
     assert err.max() < 1e-11, (err, int(it.max()), int(ou.max()))
 
 
+@pytest.mark.parametrize("order", [1, 2])
+def test_source_with_energy_opacity_and_injection_matches_oracle(torch_dev, orc, order):
+    torch, dev = torch_dev
+    w = W.config3(n=(20, 12, 10), precision="fp64", v_order=order)
+    _say("source kE + S", order, w.n)
+    y = _rough_state(w, 13, fmax=0.5)
+    rng = np.random.default_rng(21)
+    kE = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, w.kappa_P.shape)
+    kF = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, w.kappa_P.shape)
+    w.kappa_F = kF
+    tau = w.dt
+    j = rng.uniform(0.0, 1.0, w.kappa_P.shape) * w.params["a_r"] / tau
+    ref, st, _, _, _ = orc.source(w.params, y, w.rho, w.kappa_P, kF, tau, kE=kE, jS=j)
+    assert st == 0
+    S = _solver(torch_dev, w)
+    kEd, jd = _to(torch_dev, kE), _to(torch_dev, j)
+    S.set_kappa_E(kEd)
+    S.set_radiation_source(jd)
+    yd = _to(torch_dev, y)
+    S.source(yd, tau)
+    err = _rel_err(yd.cpu().numpy(), ref, range(w.nvar))
+    assert err.max() < 1e-11, err
+
+
 # ------------------------------------------------------------ stage 1 --
 def test_stage1_matches_oracle(torch_dev, orc):
     torch, dev = torch_dev
@@ -201,6 +225,34 @@ STEP_CASES = {
     "c5_small_eps_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed",
                                              hll_eps_cells=2.0), MIXED_TOL),
 }
+
+
+KE_SRC_CASES = {
+    "c2_small_kE_src": (lambda: W.config2(n=(40, 36, 20), nsteps=10), FP64_TOL),
+    "c4_small_kE_src_order1": (lambda: W.config4(n=(72, 40), nsteps=10, v_order=1), FP64_TOL),
+    "c5_small_kE_src_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6), MIXED_TOL),
+}
+
+
+@pytest.mark.parametrize("case", sorted(KE_SRC_CASES))
+def test_steps_with_energy_opacity_and_injection_match_oracle(torch_dev, orc, case):
+    mk, tol = KE_SRC_CASES[case]
+    w = mk()
+    _say("steps kE + S", case, w.n, w.nsteps, w.params["precision"])
+    rng = np.random.default_rng(31)
+    kE = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, w.kappa_P.shape)
+    j = rng.uniform(0.0, 0.5, w.kappa_P.shape) * w.y0[0] / (w.nsteps * w.dt)   # up to +50 % of E
+    ref, st, _ = orc.step(w.params, w.y0, w.rho, w.kappa_P, w.kappa_F, w.dt, w.nsteps, kE=kE, jS=j)
+    assert st == 0
+    S = _solver(torch_dev, w)
+    kEd, jd = _to(torch_dev, kE), _to(torch_dev, j)
+    S.set_kappa_E(kEd)
+    S.set_radiation_source(jd)
+    yd = _to(torch_dev, w.y0)
+    S.step(yd, w.dt, w.nsteps)
+    err = _rel_err(yd.cpu().numpy(), ref, range(w.nvar))
+    _say("  max rel err per field", err)
+    assert err.max() < tol, err
 
 
 @pytest.mark.parametrize("case", sorted(STEP_CASES))

@@ -297,7 +297,7 @@ def _four_force(z, zt_rho, p, chiP, chiE, chiF, order, nd):
     return -mcG0, -mG
 
 
-def _dense_newton(zt, rho, p, chiP, chiE, chiF, tau, order, nd):
+def _dense_newton(zt, rho, p, chiP, chiE, chiF, tau, order, nd, S=0.0):
     c, ch = p["c"], p["chat"]
     scale = np.abs(zt).copy()
     scale[0] = abs(zt[0])
@@ -311,7 +311,7 @@ def _dense_newton(zt, rho, p, chiP, chiE, chiF, tau, order, nd):
         cG0, G = _four_force(z, rho, p, chiP, chiE, chiF, order, nd)
         r = np.empty_like(z)
         r[0] = z[0] - zt[0] - tau * cG0
-        r[1] = z[1] - zt[1] + tau * (ch / c) * cG0
+        r[1] = z[1] - zt[1] - S + tau * (ch / c) * cG0
         r[2:2 + nd] = z[2:2 + nd] - zt[2:2 + nd] + tau * ch * c * G
         r[2 + nd:] = z[2 + nd:] - zt[2 + nd:] - tau * G
         return r / scale
@@ -378,3 +378,64 @@ def test_source_solves_the_fully_implicit_local_system(orc, order):
             np.testing.assert_allclose(got[2:5], z[2:5], rtol=0, atol=1e-9 * Fsc)
             psc = np.abs(z[5:8]).max() + Fsc / (c * chat)
             np.testing.assert_allclose(got[5:8], z[5:8], rtol=0, atol=1e-9 * psc)
+
+
+# ---------------- energy-mean opacity and the radiation source S (Sec. 3.3) --
+@pytest.mark.parametrize("order", [1, 2])
+def test_source_with_energy_mean_opacity_and_radiation_source(orc, order):
+    # chi_E != chi_P and a source S = j tau in eq. (FGFR): the result is the
+    # solution of the full local system with the extra S in the energy equation
+    rng = np.random.default_rng(300 + order)
+    nd, ncell = 3, 40
+    p = W.base_params(3, (ncell, 1, 1), 1.0, (0, 0, 0), closure="eddington", v_order=order)
+    cv = p["kB_over_mu"] / (p["gamma"] - 1)
+    c = p["c"]
+    rho = np.full(ncell, 1.0)
+    tau_cell = 10.0 ** rng.uniform(-2, 2, ncell)
+    kP = tau_cell / (rho * (1.0 / 64))
+    kE = kP * 10.0 ** rng.uniform(-0.5, 0.5, ncell)
+    kF = kP * 10.0 ** rng.uniform(-0.5, 0.5, ncell)
+    y = np.zeros((8, 1, 1, ncell))
+    Tg = rng.uniform(0.5, 2.0, ncell)
+    Tr = rng.uniform(0.5, 2.0, ncell)
+    y[0, 0, 0] = p["a_r"] * Tr ** 4
+    dirs = rng.normal(size=(3, ncell))
+    dirs /= np.linalg.norm(dirs, axis=0)
+    y[1:4, 0, 0] = rng.uniform(0, 0.3, ncell) * c * y[0, 0, 0] * dirs
+    vv = rng.normal(size=(3, ncell))
+    vv /= np.linalg.norm(vv, axis=0)
+    vv *= rng.uniform(0, 0.01, ncell) * c
+    y[5:8, 0, 0] = rho * vv
+    y[4, 0, 0] = rho * cv * Tg + 0.5 * rho * (vv ** 2).sum(axis=0)
+    tau = 0.3 * (1.0 / 64)
+    j = rng.uniform(0.0, 2.0, ncell) * p["a_r"] / tau     # S comparable to a_r T^4
+    shp = (1, 1, -1)
+    yo, st, _, _, _ = orc.source(p, y, rho.reshape(shp), kP.reshape(shp), kF.reshape(shp), tau,
+                                 kE=kE.reshape(shp), jS=j.reshape(shp))
+    assert st == 0
+    for i in range(ncell):
+        zt = np.concatenate([[y[4, 0, 0, i], y[0, 0, 0, i]], y[1:4, 0, 0, i], y[5:8, 0, 0, i]])
+        z = _dense_newton(zt, rho[i], p, rho[i] * kP[i], rho[i] * kE[i], rho[i] * kF[i], tau,
+                          order, nd, S=j[i] * tau)
+        got = np.concatenate([[yo[4, 0, 0, i], yo[0, 0, 0, i]], yo[1:4, 0, 0, i], yo[5:8, 0, 0, i]])
+        Etot = zt[0] + c * (zt[1] + j[i] * tau)
+        assert abs(got[0] - z[0]) < 1e-11 * Etot, (i, got[0], z[0])
+        assert abs(got[1] - z[1]) * c < 1e-11 * Etot, (i, got[1], z[1])
+        Fsc = np.abs(z[2:5]).max() + 1e-12 * zt[1] * c
+        np.testing.assert_allclose(got[2:5], z[2:5], rtol=0, atol=1e-9 * Fsc)
+    # energy: E_gas + (c/chat) E grows by exactly (c/chat) S
+    before = y[4] + c * y[0] + c * (j * tau).reshape(1, 1, -1)
+    after = yo[4] + c * yo[0]
+    np.testing.assert_allclose(after, before, rtol=2e-15)
+
+
+def test_source_with_injection_and_no_coupling_adds_s(orc):
+    # chi = 0: the local update is E += S only
+    p = W.base_params(1, (8,), 0.1, (0,))
+    y = _uniform(1, 8, p, 2.0 * p["a_r"], 1.3, F=[0.1 * p["a_r"]], v=[1e-4])
+    zero = np.zeros((1, 1, 8))
+    j = np.linspace(0.0, 3.0, 8).reshape(1, 1, 8)
+    yo, st, _, _, _ = orc.source(p, y, np.ones((1, 1, 8)), zero, None, 0.25, jS=j)
+    assert st == 0
+    assert np.array_equal(yo[0], y[0] + j * 0.25)
+    assert np.array_equal(yo[1:], y[1:])
