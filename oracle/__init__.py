@@ -45,6 +45,9 @@ class OracleParams(ctypes.Structure):
         ("scheme", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
         ("hll_eps_cells", ctypes.c_double),
+        ("kappa_T_power", ctypes.c_double),
+        ("inflow_E", ctypes.c_double),
+        ("inflow_F", ctypes.c_double),
     ]
 
 
@@ -113,6 +116,9 @@ def make_params(p: dict) -> OracleParams:
     op.scheme = {"pdars": 0, "rk2ssp": 1}[p.get("scheme", "pdars")]
     op.pad_ = 0
     op.hll_eps_cells = float(p.get("hll_eps_cells", 0.0))
+    op.kappa_T_power = float(p.get("kappa_T_power", 0.0))
+    op.inflow_E = float(p.get("inflow_E", 0.0))
+    op.inflow_F = float(p.get("inflow_F", 0.0))
     return op
 
 

@@ -58,7 +58,7 @@ typedef struct {
   double gamma;        // adiabatic index
   double a_r;          // radiation constant: 4 pi B / c = a_r T^4
   double kB_over_mu;   // k_B / (mu m_H): c_v = kB_over_mu / (gamma - 1)
-  int32_t bc[3];       // 0 = periodic, 1 = reflecting
+  int32_t bc[3];       // 0 = periodic, 1 = reflecting, 2 = fixed inflow state below, reflecting above
   int32_t v_order;     // 1: O(v/c) source terms, eq. (numF1); 2: O(v^2/c^2), eq. (numF2)
   int32_t newton_maxit;
   int32_t outer_maxit;
@@ -68,6 +68,9 @@ typedef struct {
   int32_t pad_;
   double hll_eps_cells;  // > 0: Skinner-type eps on the HLL energy dissipation (Sec. 4.2),
                          // eps = min(1, 1/tau), tau = hll_eps_cells * dx * face chi_F; 0: off
+  double kappa_T_power;  // opacities kappa_X(T) = kappa_X (field) * T^kappa_T_power (0: constant)
+  double inflow_E;       // bc 2 (inflow): ghost cells below the low face hold E = inflow_E,
+  double inflow_F;       //   normal F = inflow_F, tangential F = 0 (the high face reflects)
 } oracle_params;
 }
 
@@ -108,6 +111,11 @@ static inline double val(const Dual& x) { return x.v; }
 static inline double tan_(double) { return 0.0; }
 static inline double tan_(const Dual& x) { return x.d; }
 
+static inline double spow(double x, double q) { return std::pow(x, q); }
+static inline Dual spow(const Dual& x, double q) {
+  const double v = std::pow(x.v, q);
+  return Dual(v, q * v / x.v * x.d);
+}
 template <class S> static inline S smin(S a, S b) { return (b < a) ? b : a; }
 template <class S> static inline S smax(S a, S b) { return (a < b) ? b : a; }
 template <class S> static inline S sabs(S a) { using std::fabs; return fabs(a); }
@@ -243,6 +251,9 @@ static S face_eps(const oracle_params* p, S chi_a, S chi_b) {
 // Ghost rule (O2): 3 ghost layers along axis d. Periodic: wrap. Reflecting:
 // ghost -1-j mirrors cell j (and n+j mirrors n-1-j), with the normal flux
 // component F_d negated and E, tangential F copied.
+// bc 2 (inflow): above the grid as reflecting; below it the transport uses the
+// fixed inflow state (the mirror index returned here serves only the opacity of
+// the Skinner eps).
 static inline int64_t ghost_index(int64_t i, int64_t n, int bc, bool& flip) {
   flip = false;
   if (i >= 0 && i < n) return i;
@@ -288,6 +299,8 @@ static void transport(const oracle_params* p, const Grid& g, const S* y, S* s, c
           for (int r = 0; r < nr; ++r) {
             S v = y[(int64_t)r * g.N + c];
             if (flip && r == 1 + d) v = -v;
+            if (p->bc[d] == 2 && t < 0)   // fixed inflow state below the grid
+              v = (r == 0) ? S(p->inflow_E) : (r == 1 + d ? S(p->inflow_F) : S(0.0));
             ext[(size_t)(t + 3) * nr + r] = v;
           }
         }
@@ -367,11 +380,23 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
                        S kF, S kE, S Ssrc, double tau_d, int* iters_out, int* outer_out) {
   const S c = S(p->c), ch = S(p->chat);
   const S tau = S(tau_d);
-  const S chiP = rho * kP;   // Planck mean (comoving)
-  const S chiE = rho * kE;   // energy mean
-  const S chiF = rho * kF;   // flux mean
+  // Absorption coefficients (comoving) at the state's temperature: with
+  // kappa_T_power = q they are rho kappa T^q, evaluated at the current iterate
+  // (eq. Rnew: the chi carry the t+1 superscript), else constant.
+  const S chiP0 = rho * kP;   // Planck mean
+  const S chiE0 = rho * kE;   // energy mean
+  const S chiF0 = rho * kF;   // flux mean
+  S chiP = chiP0, chiE = chiE0, chiF = chiF0;
+  const bool Tdep = (p->kappa_T_power != 0.0);
+  auto set_chi = [&](S T) {
+    if (!Tdep) return;
+    const S f = spow(T, p->kappa_T_power);
+    chiP = chiP0 * f;
+    chiE = chiE0 * f;
+    chiF = chiF0 * f;
+  };
   int iters = 0, outer = 0;
-  if (val(chiP) == 0.0 && val(chiE) == 0.0 && val(chiF) == 0.0) {
+  if (val(chiP0) == 0.0 && val(chiE0) == 0.0 && val(chiF0) == 0.0) {
     // no coupling: R = 0, and the radiation only receives the source S
     E = E + Ssrc;
     if (iters_out) *iters_out = 0;
@@ -422,22 +447,30 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
     for (int j = 0; j < nd; ++j) vDv = vDv + v[j] * Dv[j];
 
     // R/(tau chat) = A(T) - B E + C  (eq. Rnew with P = D E), so
-    // E(Egas, R) = (A(T) + C - R/(tau chat)) / B.
-    S Afac, B;
-    if (p->v_order == 2) {
-      Afac = S(1.0) + S(0.5) * beta2;
-      B = chiE * (S(1.0) + S(0.5) * beta2) - (chiF - chiE) * (beta2 + vDv / (c * c));
-    } else {
-      Afac = S(1.0);
-      B = chiE;
-    }
-    const S Cc = (S(2.0) * chiE - chiF) * vF / (c * c);
+    // E(Egas, R) = (A(T) + C - R/(tau chat)) / B; B and C hold the absorption
+    // coefficients, which follow T when they depend on it.
+    S Afac, B, Cc;
+    auto set_BC = [&]() {
+      if (p->v_order == 2) {
+        Afac = S(1.0) + S(0.5) * beta2;
+        B = chiE * (S(1.0) + S(0.5) * beta2) - (chiF - chiE) * (beta2 + vDv / (c * c));
+      } else {
+        Afac = S(1.0);
+        B = chiE;
+      }
+      Cc = (S(2.0) * chiE - chiF) * vF / (c * c);
+    };
+    set_BC();
 
     // ---- inner Newton-Raphson on (E_gas, R), eq. (FGFR) and (linear) ----
     bool conv = false, vconv = false;
     int extra = 0;
     for (int it = 0; it <= p->newton_maxit + 40; ++it) {
       S T = (Egas - KE) / Cv;
+      if (Tdep) {
+        set_chi(T);
+        set_BC();
+      }
       S T2 = T * T;
       S A = chiP * ar * (T2 * T2) * Afac;
       S Er = (A + Cc - R / (tau * ch)) / B;
@@ -477,6 +510,7 @@ static int source_cell(const oracle_params* p, int nd, S& E, S* F, S& Eg, S* P, 
     // writes the inverse ratio; the two agree for chat = c).
     Enew = E0 - (ch / c) * (Egas - Eg0) + Ssrc;
     const S Tn = (Egas - KE) / Cv;
+    set_chi(Tn);   // absorption at the converged temperature for the flux and outer test
     const S Tn2 = Tn * Tn;
     const S Bn = ar * Tn2 * Tn2;
 

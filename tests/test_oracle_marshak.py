@@ -1,0 +1,137 @@
+"""Oracle pins: the asymptotic Marshak wave (Sec. 5.2): a cold medium with
+chi = 300/T^3 cm^-1 (T in keV), constant C_v = 3e15 erg cm^-3 keV^-1, driven by
+isotropic 1 keV radiation entering at x = 0, on 60 cells over 0.66 cm. The
+reference is the self-similar solution of the equilibrium-diffusion equation
+(Zel'dovich & Raizer), computed here by shooting, independently of the oracle.
+
+PD-ARS follows it at radiation CFL numbers from 0.9 to 10; the RK2-SSP comparator
+runs ahead by about a factor 2 at CFL 0.9 and cannot take CFL >> 1.
+"""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+K_PER_KEV = 1.160452e7
+A_R = 7.5657e-15 * K_PER_KEV ** 4        # erg cm^-3 keV^-4
+C_LIGHT = 2.99792458e10
+CV = 3e15                                 # erg cm^-3 keV^-1
+TB, T0 = 1.0, 1e-3
+N, L = 60, 0.66
+DX = L / N
+
+
+def marshak_params(scheme="pdars"):
+    return dict(ndim=1, n=(N,), dx=DX, c=C_LIGHT, chat=C_LIGHT, gamma=5.0 / 3.0, a_r=A_R,
+                kB_over_mu=CV * (2.0 / 3.0), bc=(2,), closure="eddington", v_order=1,
+                scheme=scheme, kappa_T_power=-3.0, inflow_E=A_R * TB ** 4, inflow_F=0.0,
+                newton_maxit=400, outer_maxit=10)
+
+
+def marshak_initial():
+    y = np.zeros((4, 1, 1, N))
+    y[0] = A_R * T0 ** 4
+    y[2] = CV * T0
+    return y, np.ones((1, 1, N)), np.full((1, 1, N), 300.0)
+
+
+def equilibrium_diffusion(t):
+    """T(x, t) = TB f(eta), eta = x / sqrt(t K1 / CV), solving
+    C(T) dT/dt = d/dx (K(T) dT/dx), C = CV + 4 a T^3, K = (4 a c / 900) T^6:
+    (f^6 f')' = -(eta/2)(C/CV) f', integrated inward from the front eta_f where
+    f ~ (3 eta_f (eta_f - eta))^(1/6), eta_f shot so that f(0) = 1."""
+    K1 = 4 * A_R * C_LIGHT / 900.0 * TB ** 6
+
+    def rhs(eta, u):
+        f, g = u
+        C = (CV + 4 * A_R * (TB * f) ** 3) / CV
+        return [g / f ** 6, -0.5 * eta * C * g / f ** 6]
+
+    def inward(etaf):
+        d = 1e-7 * etaf
+        f0 = (3.0 * etaf * d) ** (1.0 / 6.0)
+        return solve_ivp(rhs, [etaf - d, 0.0], [f0, -0.5 * etaf * f0], rtol=1e-11, atol=1e-14,
+                         dense_output=True)
+
+    lo, hi = 0.05, 20.0
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        if inward(mid).y[0, -1] > 1.0:
+            hi = mid
+        else:
+            lo = mid
+    etaf = 0.5 * (lo + hi)
+    sol = inward(etaf)
+    scale = np.sqrt(t * K1 / CV)
+
+    def T(x):
+        z = np.asarray(x) / scale
+        out = np.full(z.shape, T0)
+        inside = z < etaf
+        out[inside] = np.maximum(TB * sol.sol(np.minimum(z[inside], etaf * (1 - 1e-7)))[0], T0)
+        return out
+
+    return T, etaf * scale
+
+
+T_END = 2e-8
+X = (np.arange(N) + 0.5) * DX
+
+
+@pytest.fixture(scope="module")
+def reference():
+    T, front = equilibrium_diffusion(T_END)
+    assert 0.15 < front < 0.3
+    return T(X), front
+
+
+def _run(orc, scheme, cfl):
+    p = marshak_params(scheme)
+    y, rho, kap = marshak_initial()
+    ns = int(round(T_END / (cfl * DX / C_LIGHT)))
+    yo, st, _ = orc.step(p, y, rho, kap, None, T_END / ns, ns)
+    return yo, st
+
+
+def _x_half(T):
+    """Position where T first drops below TB/2 (linear between cell centres)."""
+    i = int(np.argmax(T < 0.5 * TB))
+    return X[i - 1] + (T[i - 1] - 0.5 * TB) / (T[i - 1] - T[i]) * DX
+
+
+@pytest.mark.parametrize("cfl", [0.9, 10.0])
+def test_pdars_marshak_wave_follows_equilibrium_diffusion(orc, reference, cfl):
+    Tref, _ = reference
+    yo, st = _run(orc, "pdars", cfl)
+    assert st == 0
+    T = yo[2, 0, 0] / CV
+    l1 = np.abs(T - Tref).sum() / Tref.sum()
+    assert l1 < 0.03, l1
+    assert abs(_x_half(T) - _x_half(Tref)) < 2 * DX
+    # radiation and gas stay in equilibrium behind the front
+    behind = Tref > 0.3
+    Trad = (yo[0, 0, 0] / A_R) ** 0.25
+    assert np.abs(Trad - T)[behind].max() < 0.02
+
+
+def test_rk2ssp_marshak_front_runs_about_twice_too_fast(orc, reference):
+    Tref, _ = reference
+    yo, st = _run(orc, "rk2ssp", 0.9)
+    assert st == 0
+    ratio = _x_half(yo[2, 0, 0] / CV) / _x_half(Tref)
+    assert 1.5 < ratio < 2.5, ratio
+
+
+def test_inflow_boundary_in_equilibrium_is_steady(orc):
+    # the inflow state equal to a uniform interior state: nothing moves
+    p = marshak_params()
+    Tu = 0.5
+    p["inflow_E"] = A_R * Tu ** 4
+    y = np.zeros((4, 1, 1, N))
+    y[0] = A_R * Tu ** 4
+    y[2] = CV * Tu
+    yo, st, _ = orc.step(p, y, np.ones((1, 1, N)), np.full((1, 1, N), 300.0), None,
+                         DX / C_LIGHT, 20)
+    assert st == 0
+    np.testing.assert_allclose(yo[0], y[0], rtol=1e-13)
+    np.testing.assert_allclose(yo[2], y[2], rtol=1e-13)
+    assert np.abs(yo[1]).max() < 1e-12 * C_LIGHT * y[0].max()
