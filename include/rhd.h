@@ -55,7 +55,10 @@ typedef enum {
   RHD_EWORKSPACE = -5   /* workspace pointer NULL, misaligned or smaller than rhd_workspace_bytes */
 } rhd_status;
 
-enum { RHD_BC_PERIODIC = 0, RHD_BC_REFLECT = 1 };
+/* RHD_BC_INFLOW: the ghost cells below the low face of the axis hold the fixed
+ * radiation state (E = inflow_E, normal F = inflow_F, tangential F = 0), the high
+ * face reflects (an entering radiation field, e.g. the Marshak wave of Sec. 5.2). */
+enum { RHD_BC_PERIODIC = 0, RHD_BC_REFLECT = 1, RHD_BC_INFLOW = 2 };
 enum { RHD_CLOSURE_M1 = 0, RHD_CLOSURE_EDDINGTON = 1 };
 enum { RHD_FP64 = 0, RHD_MIXED = 1 };
 enum { RHD_SCHEME_PDARS = 0, RHD_SCHEME_RK2SSP = 1 };
@@ -70,7 +73,8 @@ typedef struct {
   double gamma;          /* adiabatic index, > 1; c_v = kB_over_mu / (gamma - 1) per unit mass */
   double a_r;            /* radiation constant: 4 pi B / c = a_r T^4, > 0 */
   double kB_over_mu;     /* k_B / (mu m_H), > 0 */
-  int32_t bc[3];         /* RHD_BC_PERIODIC or RHD_BC_REFLECT per axis (reflect needs n >= 3) */
+  int32_t bc[3];         /* RHD_BC_PERIODIC, RHD_BC_REFLECT or RHD_BC_INFLOW per axis (the last
+                            two need n >= 3) */
   int32_t v_order;       /* 1: O(v/c) source terms, eq. numF1; 2: O(v^2/c^2): eq. numF2, or
                             with kappa_F != kappa_P the 3x3 flux system of eq. fupdate-G1 */
   int32_t precision;     /* RHD_FP64, or RHD_MIXED: transport stencil in float32, state,
@@ -86,6 +90,12 @@ typedef struct {
                             Sec. 4.2 on the energy flux, whose dissipation is multiplied by
                             eps = min(1, 1/tau) with tau = hll_eps_cells * dx * (chi_F of the two
                             cells at the face)/2, chi_F = rho kappa_F (forward only) */
+  double kappa_T_power;  /* 0: opacities are the fields. q != 0: every opacity is its field times
+                            T^q, evaluated by the local source at the Newton iterate (the chi of
+                            eq. Rnew carry the t+1 superscript); e.g. q = -3 for chi = 300/T^3
+                            (Sec. 5.2). Needs hll_eps_cells = 0; forward only */
+  double inflow_E;       /* RHD_BC_INFLOW ghost state: radiation energy density */
+  double inflow_F;       /* RHD_BC_INFLOW ghost state: flux along the axis */
 } rhd_params;
 
 /* Bytes of device workspace rhd_create needs for these parameters.
@@ -123,8 +133,9 @@ rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps);
  *     into g_kappa_P.
  * The forward steps are recomputed from state0 inside the call; each local
  * implicit solve is differentiated with the implicit function theorem at its
- * converged state. Returns RHD_EINVAL (nothing launched) for reflecting axes,
- * the RK2-SSP scheme or hll_eps_cells > 0, which the adjoint does not cover. */
+ * converged state. Returns RHD_EINVAL (nothing launched) for non-periodic axes,
+ * the RK2-SSP scheme, hll_eps_cells > 0 or kappa_T_power != 0, which the adjoint
+ * does not cover. */
 rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int32_t nsteps,
                             double* lambda, double* g_kappa_P, double* g_kappa_F);
 

@@ -30,10 +30,8 @@ def build(verbose=False, extra=()):
         if not os.path.exists(path):
             continue
         obj = os.path.join(CSRC, src + ".o")
+        # hipcc compiles the host-only .cpp as HIP too: same target and flags
         cmd = [HIPCC, *FLAGS, *extra, "-c", path, "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I",
-                   os.path.join(HERE, "..", "include"), *extra, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -61,8 +61,9 @@ std::string validate(const rhd_params* p) {
     if (d < p->ndim) {
       if (p->n[d] < 1) return "n[d] must be >= 1 on active axes";
       if (p->n[d] > (1LL << 24)) return "n[d] too large";
-      if (p->bc[d] != RHD_BC_PERIODIC && p->bc[d] != RHD_BC_REFLECT) return "bc must be periodic or reflect";
-      if (p->bc[d] == RHD_BC_REFLECT && p->n[d] < 3) return "reflecting axes need n >= 3";
+      if (p->bc[d] != RHD_BC_PERIODIC && p->bc[d] != RHD_BC_REFLECT && p->bc[d] != RHD_BC_INFLOW)
+        return "bc must be periodic, reflect or inflow";
+      if (p->bc[d] != RHD_BC_PERIODIC && p->n[d] < 3) return "reflecting and inflow axes need n >= 3";
     } else if (p->n[d] != 1) {
       return "axes beyond ndim must have n = 1";
     }
@@ -84,6 +85,10 @@ std::string validate(const rhd_params* p) {
   if (!(p->outer_rtol >= 0.0) || !std::isfinite(p->outer_rtol)) return "outer_rtol must be >= 0";
   if (!(p->hll_eps_cells >= 0.0) || !std::isfinite(p->hll_eps_cells))
     return "hll_eps_cells must be >= 0 and finite";
+  if (!std::isfinite(p->kappa_T_power)) return "kappa_T_power must be finite";
+  if (p->kappa_T_power != 0.0 && p->hll_eps_cells > 0.0)
+    return "kappa_T_power != 0 needs hll_eps_cells = 0";
+  if (!std::isfinite(p->inflow_E) || !std::isfinite(p->inflow_F)) return "inflow state must be finite";
   return "";
 }
 
@@ -94,7 +99,6 @@ struct Layout {
 Layout layout(const rhd_params* p, int adj_len) {
   const size_t N = (size_t)ncells(p);
   const size_t nv = (size_t)nvar_of(p);
-  const size_t nr = (size_t)(1 + p->ndim);
   Layout L{};
   size_t off = 0;
   L.err = off;
@@ -144,6 +148,9 @@ rhd::DevParams make_dev(const rhd_params* p, bool alias) {
   d.kF_alias = alias ? 1 : 0;
   d.scheme = p->scheme;
   d.eps_dx = p->hll_eps_cells * p->dx;
+  d.kT_pow = p->kappa_T_power;
+  d.inflow_E = p->inflow_E;
+  d.inflow_F = p->inflow_F;
   return d;
 }
 
@@ -355,6 +362,8 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
     return set_err(h, RHD_EINVAL, -1, "the adjoint is available for the PD-ARS scheme only");
   if (h->p.hll_eps_cells > 0.0)
     return set_err(h, RHD_EINVAL, -1, "the adjoint does not cover the HLL eps correction");
+  if (h->p.kappa_T_power != 0.0)
+    return set_err(h, RHD_EINVAL, -1, "the adjoint does not cover temperature-dependent opacities");
   for (int d = 0; d < h->p.ndim; ++d)
     if (h->p.bc[d] != RHD_BC_PERIODIC)
       return set_err(h, RHD_EINVAL, -1, "the adjoint supports periodic axes only");

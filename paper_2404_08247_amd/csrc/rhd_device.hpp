@@ -204,13 +204,25 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
 // inv_tch = 1/(tau chat) is passed in (uniform over a launch). kE: energy-mean
 // opacity (kP when it is not a separate field); Ssrc: the radiation source S of
 // eq. FGFR over this sub-step (0 when absent).
-template <int ND>
+//
+// TDEP: every absorption coefficient is chi_X = rho kappa_X T^q (q = kT_pow),
+// taken at the temperature of the current Newton iterate (the chi of eq. Rnew
+// are at t+1) and at the converged T for the flux update and the outer test.
+// All of A, B and C of E(E_gas, R) are linear in the chi, so only the R/(tau chat)
+// term and dF_R/dR see the factor: with g = T^-q and the pass coefficients taken
+// at the field values (chi_X = rho kappa_X),
+//   E = (A + C - g R/(tau chat)) / B,  dF_R/dR = -g/(tau chat chi_E) - 1,
+// while dF_R/dE_gas keeps the ratio chi_P/chi_E, which T^q leaves unchanged (the
+// simplified Jacobian carries no d chi/dT).
+template <int ND, bool TDEP = false>
 __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double& Eg, double* Pm,
                                 double rho, double kP, double kF, double kE, double Ssrc,
                                 double tau, double inv_tch) {
-  const double chiP = rho * kP;
-  const double chiE = rho * kE;
-  const double chiF = rho * kF;
+  double chiP = rho * kP;
+  double chiE = rho * kE;
+  double chiF = rho * kF;
+  // field values (the pass coefficients below); chiP/E/F follow T when TDEP
+  const double chiP0 = chiP, chiE0 = chiE, chiF0 = chiF;
   if (chiP == 0.0 && chiE == 0.0 && chiF == 0.0) {   // no coupling: E += S only
     E += Ssrc;
     return 0u;
@@ -242,7 +254,8 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   const double tol = P.newton_rtol * (Eg0 + k_cc * (E0 + Ssrc));
   // simplified Jacobian (fixed for the call): dF_R/dR and the T^3 factor of
   // dF_R/dE_gas = (1/C_v) d/dT (chi_P/chi_E a T^4)
-  const double J22 = -inv_tch * inv_chiE - 1.0;
+  const double J22c = -inv_tch * inv_chiE;
+  const double J22 = J22c - 1.0;
   const double J21c = 4.0 * ar * inv_Cv * (kP == kE ? 1.0 : chiP * inv_chiE);
   const double ctau = ch * tau;
   // order 1: 1/B = 1/chi_E and the flux denominator do not change between passes
@@ -270,28 +283,29 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     double inv_B, inv_den, a2 = 1.0;
     if (o2) {
       const double a1 = 1.0 + 0.5 * b2;
-      a2 = 1.0 + ctau * chiF * a1;
-      if (chiF == chiE) {
+      a2 = 1.0 + ctau * chiF0 * a1;
+      if (chiF0 == chiE0) {
         const double q = rcp(a1 * a2);
         inv_B = q * a2 * inv_chiE;
         inv_den = q * a1;
       } else {
-        inv_B = rcp(chiE * a1 - (chiF - chiE) * (b2 + vDv * P.inv_c2));
+        inv_B = rcp(chiE0 * a1 - (chiF0 - chiE0) * (b2 + vDv * P.inv_c2));
         inv_den = rcp(a2);
       }
     } else {
       inv_B = inv_chiE;
       inv_den = inv_den_o1;
     }
-    const double Cc = (2.0 * chiE - chiF) * vF * P.inv_c2;
-    const double Aco = chiP * ar * (o2 ? 1.0 + 0.5 * b2 : 1.0);
+    const double Cc = (2.0 * chiE0 - chiF0) * vF * P.inv_c2;
+    const double Aco = chiP0 * ar * (o2 ? 1.0 + 0.5 * b2 : 1.0);
 
     // ---- inner Newton on (E_gas, R) ----
     bool conv = false;
     for (int it = 0;; ++it) {
       const double T = (Egas - KE) * inv_Cv;
       const double T2 = T * T;
-      const double Er = (Aco * T2 * T2 + Cc - R * inv_tch) * inv_B;
+      const double gT = TDEP ? pow(T, -P.kT_pow) : 1.0;   // chi(field) / chi(T)
+      const double Er = (Aco * T2 * T2 + Cc - R * inv_tch * gT) * inv_B;
       const double FG = Egas - Eg0 + k_cc * R;
       const double FR = Er - E0 - (R + Ssrc);
       if (fabs(FG) < tol && k_cc * fabs(FR) < tol) {
@@ -300,8 +314,9 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       }
       if (it >= P.newton_maxit) break;
       const double J21 = J21c * T2 * T;
-      const double inv_det = rcp1(J22 - k_cc * J21);
-      Egas += (k_cc * FR - J22 * FG) * inv_det;
+      const double J22t = TDEP ? J22c * gT - 1.0 : J22;
+      const double inv_det = rcp1(J22t - k_cc * J21);
+      Egas += (k_cc * FR - J22t * FG) * inv_det;
       R += (J21 * FG - FR) * inv_det;
     }
     if (!conv) {
@@ -318,6 +333,18 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     // when chi_F = chi_E).
     Enew = E0 - P.chat_over_c * (Egas - Eg0) + Ssrc;
     const double Tn = (Egas - KE) * inv_Cv;
+    if constexpr (TDEP) {   // absorption at the converged T for the flux and the outer test
+      const double fT = pow(Tn, P.kT_pow);
+      chiP = chiP0 * fT;
+      chiE = chiE0 * fT;
+      chiF = chiF0 * fT;
+      if (o2) {
+        a2 = 1.0 + ctau * chiF * (1.0 + 0.5 * b2);
+        inv_den = rcp(a2);
+      } else {
+        inv_den = rcp(1.0 + ctau * chiF);
+      }
+    }
     const double Tn2 = Tn * Tn;
     const double Bn = ar * Tn2 * Tn2;
     const double xv = chiP * Bn + (chiF - chiE) * Enew;

@@ -15,7 +15,8 @@
 //    monotonised right edge of cell k and the z-flux below), so every z-face is
 //    computed once and z needs neither LDS nor a halo exchange.
 // Halo cells come from the ghost rule (periodic wrap, or mirror with the normal
-// flux component negated), applied on load.
+// flux component negated; below an inflow axis, the fixed inflow state), applied
+// on load.
 #include <climits>
 
 #include "rhd_device.hpp"
@@ -73,13 +74,25 @@ __device__ __forceinline__ void report(unsigned long long* err, long long cell, 
   atomicOr(reinterpret_cast<unsigned int*>(err + 1), bits);
 }
 
-// EPS: the optional Skinner-type eps on the HLL energy flux (a separate
-// instantiation: it stages chi_F = rho kappa_F of the tile in LDS).
-template <int ND, int MODE, typename TT, bool EPS>
+// Value of radiation variable r (E, F_1..F_ND) in a ghost cell below an inflow
+// axis: the fixed inflow state, with its flux along the axis.
+__device__ __forceinline__ double inflow_value(const DevParams& P, int r, int axis) {
+  return r == 0 ? P.inflow_E : (r == 1 + axis ? P.inflow_F : 0.0);
+}
+
+// Kernel variants (separate instantiations, so the plain path carries none of
+// their code): VAR_EPS, the optional Skinner-type eps on the HLL energy flux,
+// which stages chi_F = rho kappa_F of the tile in LDS; VAR_TDEP, opacities that
+// follow the temperature in the local source.
+enum { VAR_PLAIN = 0, VAR_EPS = 1, VAR_TDEP = 2 };
+
+template <int ND, int MODE, typename TT, int VAR>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(RHD_STAGE_WAVES)))
 k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw,
         const double* __restrict__ rho, const double* __restrict__ kP,
         const double* __restrict__ kF, double dt, int zchunk, unsigned long long* err) {
+  constexpr bool EPS = (VAR == VAR_EPS);
+  constexpr bool TDEP = (VAR == VAR_TDEP);
   constexpr int TX = TileShape<ND>::TX;
   constexpr int TY = TileShape<ND>::TY;
   constexpr int NR = 1 + ND;                 // radiation variables E, F_1..F_ND
@@ -162,11 +175,12 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     for (int m = 0; m < 6; ++m) {
       bool flip;
       const int gz = ghost(z0 - 3 + m, nz, P.bc[2], flip);
+      const bool fixz = (z0 - 3 + m < 0) && P.bc[2] == BC_INFLOW;
       const long long q = gz * plane + colq;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const double val = ys[r * N + q];
-        w[m][r] = (flip && r == 3) ? -val : val;
+        w[m][r] = fixz ? inflow_value(P, r, 2) : ((flip && r == 3) ? -val : val);
       }
     }
     double Um[NR], Up[NR];
@@ -211,6 +225,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   long long hoff = -1;
   int htile = 0;
   bool hfx = false, hfy = false;
+  int hfix = -1;   // axis whose inflow state this halo position holds (-1: none)
   if (tid < NHX + NHY) {
     int lx, ly;
     if (tid < NHX) {
@@ -225,6 +240,9 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     }
     const int sx = ghost(x0 + lx - HALO, nx, P.bc[0], hfx);
     const int sy = (ND >= 2) ? ghost(y0 + ly - HALO, ny, P.bc[1], hfy) : 0;
+    // halo positions lie outside the tile along one axis only (no corners)
+    if (x0 + lx - HALO < 0 && P.bc[0] == BC_INFLOW) hfix = 0;
+    if (ND >= 2 && y0 + ly - HALO < 0 && P.bc[1] == BC_INFLOW) hfix = 1;
     hoff = (long long)sy * nx + sx;
     htile = ly * TW + lx;
   }
@@ -293,7 +311,8 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     if (hoff >= 0) {
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        s_area[r][htile] = ((hfx && r == 1) || (hfy && r == 2)) ? -hv[r] : hv[r];
+        s_area[r][htile] = hfix >= 0 ? inflow_value(P, r, hfix)
+                                     : (((hfx && r == 1) || (hfy && r == 2)) ? -hv[r] : hv[r]);
     }
     double chi_k = 0.0, chi_k1 = 0.0;   // chi_F of the own cell at planes k and k+1 (EPS)
     if constexpr (EPS) {
@@ -492,8 +511,8 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       // of the step with the full dt
       const unsigned st = (MODE == MODE_STAGE1 && P.scheme == 1)
                               ? 0u
-                              : source_cell<ND>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, pre_ke,
-                                                pre_j * tau_src, tau_src, inv_tch);
+                              : source_cell<ND, TDEP>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, pre_ke,
+                                                      pre_j * tau_src, tau_src, inv_tch);
       if (st) report(err, q, st);
       yw[q] = E;
 #pragma unroll
@@ -506,7 +525,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
 }
 
 // Source only (no transport), one cell per thread.
-template <int ND>
+template <int ND, bool TDEP>
 __global__ void __launch_bounds__(NTHREADS)
 k_source(DevParams P, double* y, const double* __restrict__ rho, const double* __restrict__ kP,
          const double* __restrict__ kF, double tau, unsigned long long* err) {
@@ -520,9 +539,9 @@ k_source(DevParams P, double* y, const double* __restrict__ rho, const double* _
     Pm[k] = y[(2 + ND + k) * N + q];
   }
   const double kp = kP[q];
-  const unsigned st = source_cell<ND>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q],
-                                     P.kE ? P.kE[q] : kp, P.jS ? P.jS[q] * tau : 0.0, tau,
-                                     rcp(tau * P.chat));
+  const unsigned st = source_cell<ND, TDEP>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q],
+                                           P.kE ? P.kE[q] : kp, P.jS ? P.jS[q] * tau : 0.0, tau,
+                                           rcp(tau * P.chat));
   if (st) report(err, q, st);
   y[q] = E;
   y[(1 + ND) * N + q] = Eg;
@@ -575,7 +594,7 @@ k_totals(DevParams P, const double* __restrict__ y, double* __restrict__ partial
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int ND, int MODE, typename TT, bool EPS>
+template <int ND, int MODE, typename TT, int VAR>
 static hipError_t launch_nd(const DevParams& P, const double* ys, const double* yo, double* yw,
                             const double* rho, const double* kP, const double* kF, double dt,
                             unsigned long long* err, hipStream_t s) {
@@ -591,7 +610,7 @@ static hipError_t launch_nd(const DevParams& P, const double* ys, const double* 
     if (zchunk > nz) zchunk = nz;
   }
   const int gzn = (nz + zchunk - 1) / zchunk;
-  hipLaunchKernelGGL((k_stage<ND, MODE, TT, EPS>), dim3(gxn, gyn, gzn), dim3(NTHREADS), 0, s, P, ys,
+  hipLaunchKernelGGL((k_stage<ND, MODE, TT, VAR>), dim3(gxn, gyn, gzn), dim3(NTHREADS), 0, s, P, ys,
                      yo, yw, rho, kP, kF, dt, zchunk, err);
   return hipGetLastError();
 }
@@ -600,14 +619,20 @@ template <int MODE, typename TT>
 static hipError_t launch_mode(const DevParams& P, const double* ys, const double* yo, double* yw,
                               const double* rho, const double* kP, const double* kF, double dt,
                               unsigned long long* err, hipStream_t s) {
-  const bool eps = P.eps_dx > 0.0;
-  switch (P.ndim) {
-    case 1: return eps ? launch_nd<1, MODE, TT, true>(P, ys, yo, yw, rho, kP, kF, dt, err, s)
-                       : launch_nd<1, MODE, TT, false>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
-    case 2: return eps ? launch_nd<2, MODE, TT, true>(P, ys, yo, yw, rho, kP, kF, dt, err, s)
-                       : launch_nd<2, MODE, TT, false>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
-    case 3: return eps ? launch_nd<3, MODE, TT, true>(P, ys, yo, yw, rho, kP, kF, dt, err, s)
-                       : launch_nd<3, MODE, TT, false>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+  // the host rejects eps together with temperature-dependent opacities; the
+  // transport-only mode runs no source, so it never needs VAR_TDEP
+  const int var = P.eps_dx > 0.0 ? VAR_EPS
+                                 : ((P.kT_pow != 0.0 && MODE != MODE_TRANSPORT) ? VAR_TDEP : VAR_PLAIN);
+  switch (P.ndim * 4 + var) {
+    case 4 + VAR_PLAIN: return launch_nd<1, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 4 + VAR_EPS: return launch_nd<1, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 4 + VAR_TDEP: return launch_nd<1, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 8 + VAR_PLAIN: return launch_nd<2, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 8 + VAR_EPS: return launch_nd<2, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 8 + VAR_TDEP: return launch_nd<2, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 12 + VAR_PLAIN: return launch_nd<3, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 12 + VAR_EPS: return launch_nd<3, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 12 + VAR_TDEP: return launch_nd<3, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -632,10 +657,14 @@ hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* 
 hipError_t launch_source(const DevParams& P, double* y, const double* rho, const double* kP,
                          const double* kF, double tau, unsigned long long* err, hipStream_t s) {
   const unsigned blocks = (unsigned)((P.N + NTHREADS - 1) / NTHREADS);
-  switch (P.ndim) {
-    case 1: hipLaunchKernelGGL(k_source<1>, dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 2: hipLaunchKernelGGL(k_source<2>, dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 3: hipLaunchKernelGGL(k_source<3>, dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+  const bool tdep = P.kT_pow != 0.0;
+  switch (P.ndim * 2 + (tdep ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_source<1, false>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 3: hipLaunchKernelGGL((k_source<1, true>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 4: hipLaunchKernelGGL((k_source<2, false>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 5: hipLaunchKernelGGL((k_source<2, true>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 6: hipLaunchKernelGGL((k_source<3, false>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 7: hipLaunchKernelGGL((k_source<3, true>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -28,6 +28,8 @@ struct DevParams {
   int kF_alias;       // 1: kappa_F == kappa_P
   int scheme;         // 0 PD-ARS, 1 RK2-SSP comparator
   double eps_dx;      // hll_eps_cells * dx (0: plain HLL)
+  double kT_pow;      // opacity temperature exponent (0: constant opacities)
+  double inflow_E, inflow_F;   // ghost state of RHD_BC_INFLOW axes
   const double* kE;   // energy-mean opacity per unit mass (device), or null: kappa_P
   const double* jS;   // radiation injection rate per unit volume (device), or null: none
 };
@@ -37,6 +39,8 @@ struct DevParams {
 enum : unsigned { ERR_NEWTON = 1u, ERR_NONPHYS = 2u };
 
 enum StageMode : int { MODE_STAGE1 = 0, MODE_STAGE2 = 1, MODE_TRANSPORT = 2 };
+// boundary kinds of DevParams::bc (the values of the public header's RHD_BC_*)
+enum BoundaryKind : int { BC_PERIODIC = 0, BC_REFLECT = 1, BC_INFLOW = 2 };
 
 // Forward launchers (rhd_forward.hip). All return hipSuccess or the launch error.
 hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* ysten,

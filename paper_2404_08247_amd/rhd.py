@@ -44,6 +44,9 @@ class RHDParams(ctypes.Structure):
         ("newton_rtol", ctypes.c_double),
         ("outer_rtol", ctypes.c_double),
         ("hll_eps_cells", ctypes.c_double),
+        ("kappa_T_power", ctypes.c_double),
+        ("inflow_E", ctypes.c_double),
+        ("inflow_F", ctypes.c_double),
     ]
 
 
@@ -120,6 +123,9 @@ def make_params(p: dict) -> RHDParams:
     rp.newton_rtol = float(p.get("newton_rtol", 1e-13))
     rp.outer_rtol = float(p.get("outer_rtol", 1e-13))
     rp.hll_eps_cells = float(p.get("hll_eps_cells", 0.0))
+    rp.kappa_T_power = float(p.get("kappa_T_power", 0.0))
+    rp.inflow_E = float(p.get("inflow_E", 0.0))
+    rp.inflow_F = float(p.get("inflow_F", 0.0))
     return rp
 
 

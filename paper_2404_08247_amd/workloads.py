@@ -281,4 +281,36 @@ def config5(n: Sequence[int] = (320, 320, 320), nsteps: int = 100, ckpt_every: i
                     objective_mask=central_patch(p["n"], 3, max(2, nx // 5)), ckpt_every=ckpt_every)
 
 
+# The asymptotic Marshak wave (Sec. 5.2), in cgs with temperatures in keV.
+MARSHAK = dict(a_r=7.5657e-15 * 1.160452e7 ** 4,   # erg cm^-3 keV^-4
+               c=2.99792458e10, cv=3e15,            # erg cm^-3 keV^-1 (rho = 1)
+               kappa=300.0, T_hot=1.0, T_cold=1e-3, length=0.66, t_end=2e-8)
+
+
+def marshak(n: int = 60, cfl: float = 10.0, scheme: str = "pdars", t_end: Optional[float] = None,
+            **over) -> Workload:
+    """1-D Marshak wave: a cold (T = 1e-3 keV) static medium of density 1 with
+    chi = 300 / T^3 cm^-1 (kappa = 300 scaled by T^-3 in the source) and
+    C_v = 3e15 erg cm^-3 keV^-1, driven through x = 0 by radiation at 1 keV
+    (inflow boundary; the far end reflects); Eddington closure, order-1 source,
+    chat = c. dt = cfl dx / c, rounded so that an integer number of steps ends at
+    t_end (default 2e-8 s)."""
+    m = MARSHAK
+    t_end = m["t_end"] if t_end is None else t_end
+    dx = m["length"] / n
+    p = dict(ndim=1, n=(n, 1, 1), dx=dx, c=m["c"], chat=m["c"], gamma=5.0 / 3.0, a_r=m["a_r"],
+             kB_over_mu=m["cv"] * (2.0 / 3.0), bc=(2, 0, 0), closure="eddington", v_order=1,
+             precision="fp64", scheme=scheme, newton_rtol=1e-13, outer_rtol=1e-13,
+             newton_maxit=400, outer_maxit=10, kappa_T_power=-3.0,
+             inflow_E=m["a_r"] * m["T_hot"] ** 4, inflow_F=0.0)
+    p.update(over)
+    shape = (1, 1, n)
+    y = np.zeros((4,) + shape)
+    y[0] = m["a_r"] * m["T_cold"] ** 4
+    y[2] = m["cv"] * m["T_cold"]
+    nsteps = max(1, int(round(t_end / (cfl * dx / m["c"]))))
+    return Workload(f"marshak_1d_{n}_cfl{cfl:g}_{scheme}", 1, p["n"], p, y, np.ones(shape),
+                    np.full(shape, m["kappa"]), None, t_end / nsteps, nsteps)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

@@ -31,12 +31,13 @@ def test_library_exports_every_declared_symbol():
 def test_params_struct_layout_matches_header():
     from paper_2404_08247_amd import rhd
     # int32 ndim, closure; int64 n[3]; 6 doubles; int32 bc[3], v_order, precision,
-    # newton_maxit, outer_maxit, scheme; 3 doubles
-    assert ctypes.sizeof(rhd.RHDParams) == 8 + 24 + 48 + 32 + 24
+    # newton_maxit, outer_maxit, scheme; 6 doubles
+    assert ctypes.sizeof(rhd.RHDParams) == 8 + 24 + 48 + 32 + 48
     assert rhd.RHDParams.n.offset == 8
     assert rhd.RHDParams.bc.offset == 80
     assert rhd.RHDParams.newton_rtol.offset == 112
     assert rhd.RHDParams.hll_eps_cells.offset == 128
+    assert rhd.RHDParams.inflow_F.offset == 152
 
 
 def _ws(p, k=0):
@@ -53,7 +54,9 @@ def test_workspace_size_and_validation():
     bad = [dict(p, chat=2.0), dict(p, chat=0.0), dict(p, dx=-1.0), dict(p, gamma=1.0),
            dict(p, v_order=3), dict(p, ndim=4), dict(p, n=(16, 12, 0)),
            dict(p, newton_maxit=0), dict(p, a_r=0.0), dict(p, newton_rtol=0.0),
-           dict(p, hll_eps_cells=-1.0), dict(p, hll_eps_cells=float("inf"))]
+           dict(p, hll_eps_cells=-1.0), dict(p, hll_eps_cells=float("inf")),
+           dict(p, kappa_T_power=-3.0, hll_eps_cells=1.0), dict(p, bc=(3, 0, 0)),
+           dict(p, inflow_E=float("nan"))]
     for b in bad:
         assert _ws(b) == 0, b
     # reflecting axis needs >= 3 cells; axes beyond ndim must be 1
@@ -100,7 +103,8 @@ def test_adjoint_rejects_what_it_does_not_differentiate():
     L = rhd.lib
     fake = ctypes.c_void_p(1 << 20)
     base = W.config4(n=(16, 12)).params
-    for bad in (dict(base, bc=(1, 0)), dict(base, scheme="rk2ssp"), dict(base, hll_eps_cells=1.0)):
+    for bad in (dict(base, bc=(1, 0)), dict(base, scheme="rk2ssp"), dict(base, hll_eps_cells=1.0),
+                dict(base, bc=(2, 0)), dict(base, kappa_T_power=-3.0)):
         rp = rhd.make_params(bad)
         nb = L.rhd_workspace_bytes(ctypes.byref(rp), 2)
         assert nb > 0

@@ -1,0 +1,204 @@
+"""GPU parity for the inflow boundary and temperature-dependent opacities, the
+two options that the Marshak wave of Sec. 5.2 needs (chi = 300/T^3, radiation
+entering through x = 0), called through the C-ABI against the CPU oracle.
+
+Bars (L-inf error per field relative to the field's max |oracle value|): 1e-12
+for one transport call, 1e-11 for one source call, 1e-10 for FP64 runs (the
+full Marshak run of 5451 PD-ARS steps at CFL 10 included, which is also held
+to the self-similar solution like the oracle's own run), 1e-5 in mixed
+precision.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_08247_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+def _to(torch_dev, a):
+    torch, dev = torch_dev
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+def _solver(torch_dev, w):
+    from paper_2404_08247_amd import rhd
+    kF = None if w.kappa_F is None else _to(torch_dev, w.kappa_F)
+    return rhd.Solver(w.params, _to(torch_dev, w.rho), _to(torch_dev, w.kappa_P), kF, 0)
+
+
+def _rel_err(got, ref, rows):
+    out = []
+    for v in rows:
+        sc = np.abs(ref[v]).max()
+        d = np.abs(got[v] - ref[v]).max()
+        out.append(d / sc if sc > 0 else d)
+    return np.array(out)
+
+
+def _rough_state(w, seed, fmax=0.5):
+    rng = np.random.default_rng(seed)
+    y = w.y0.copy()
+    nd = w.ndim
+    dirs = rng.normal(size=(nd,) + y[0].shape)
+    dirs /= np.linalg.norm(dirs, axis=0) + 1e-300
+    f = rng.uniform(0, fmax, y[0].shape)
+    for d in range(nd):
+        y[1 + d] = f * w.params["c"] * y[0] * dirs[d]
+    return y
+
+
+def _inflow(w, bc, q=0.0):
+    """The workload with the given boundary kinds and opacity exponent q; the
+    inflow state is twice the initial state's largest E, with a flux 0.3 c E_in
+    into the domain."""
+    Ein = 2.0 * w.y0[0].max()
+    w.params = dict(w.params, bc=tuple(bc) + (0,) * (3 - len(bc)), kappa_T_power=q,
+                    inflow_E=Ein, inflow_F=0.3 * w.params["c"] * Ein)
+    return w
+
+
+def _with_kF(w, seed=4):
+    rng = np.random.default_rng(seed)
+    w.kappa_F = w.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, w.kappa_P.shape)
+    return w
+
+
+# --------------------------------------------------- transport, inflow --
+INFLOW_TRANSPORT_CASES = {
+    "1d_inflow_m1": lambda: _inflow(W.config1(n=300), (2,)),
+    "1d_inflow_edd": lambda: _inflow(W.config1(n=61, closure="eddington"), (2,)),
+    "2d_inflow_xy": lambda: _inflow(W.config4(n=(70, 21)), (2, 2)),
+    "2d_inflow_y": lambda: _inflow(W.config4(n=(37, 19)), (0, 2)),
+    "3d_inflow_xz": lambda: _inflow(W.config2(n=(40, 20, 19)), (2, 1, 2)),
+    "3d_inflow_all": lambda: _inflow(W.config5(n=(33, 18, 21), precision="fp64"), (2, 2, 2)),
+}
+
+
+@pytest.mark.parametrize("case", sorted(INFLOW_TRANSPORT_CASES))
+def test_transport_with_inflow_matches_oracle(torch_dev, orc, case):
+    torch, dev = torch_dev
+    w = INFLOW_TRANSPORT_CASES[case]()
+    _say("transport inflow", case, w.n, w.params["bc"])
+    y = _rough_state(w, 17, fmax=0.9)
+    ref = orc.transport(w.params, y)
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, y)
+    sd = torch.zeros_like(yd)
+    S.transport(yd, sd)
+    err = _rel_err(sd.cpu().numpy(), ref, range(1 + w.ndim))
+    assert err.max() < 1e-12, err
+    # the inflow ghosts differ from reflecting ones: the result changes
+    refl = orc.transport(dict(w.params, bc=tuple(min(b, 1) for b in w.params["bc"])), y)
+    assert np.abs(refl[0] - ref[0]).max() > 1e-6 * np.abs(ref[0]).max()
+
+
+# ---------------------------------------- source, T-dependent opacity --
+TDEP_SOURCE_CASES = {
+    "c2_q-3": lambda: W.config2(n=(24, 16, 12), kappa_T_power=-3.0),
+    "c3_order1_kF_q-1.5": lambda: _with_kF(W.config3(n=(20, 12, 10), precision="fp64", v_order=1,
+                                                     kappa_T_power=-1.5)),
+    "c3_order2_kF_q-3": lambda: _with_kF(W.config3(n=(20, 12, 10), precision="fp64",
+                                                   kappa_T_power=-3.0)),
+    "c4_order2_q2": lambda: W.config4(n=(40, 24), kappa_T_power=2.0),
+    "c5_m1_q-3.5": lambda: W.config5(n=(20, 12, 10), precision="fp64", kappa_T_power=-3.5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(TDEP_SOURCE_CASES))
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_source_with_temperature_dependent_opacity_matches_oracle(torch_dev, orc, case, theta):
+    w = TDEP_SOURCE_CASES[case]()
+    _say("source T-dep", case, theta, w.n)
+    y = _rough_state(w, 19)
+    tau = theta * w.dt
+    ref, st, fc, it, ou = orc.source(w.params, y, w.rho, w.kappa_P, w.kappa_F, tau)
+    assert st == 0
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, y)
+    S.source(yd, tau)
+    err = _rel_err(yd.cpu().numpy(), ref, range(w.nvar))
+    assert err.max() < 1e-11, (err, int(it.max()), int(ou.max()))
+    # the exponent matters: constant opacities give another result
+    plain, _, _, _, _ = orc.source(dict(w.params, kappa_T_power=0.0), y, w.rho, w.kappa_P,
+                                   w.kappa_F, tau)
+    assert np.abs(plain[1 + w.ndim] - ref[1 + w.ndim]).max() > 1e-9 * np.abs(ref[1 + w.ndim]).max()
+
+
+# ------------------------------------------------------- whole steps --
+STEP_CASES = {
+    "c2_small_q-1.5_inflow_xz": (lambda: _inflow(W.config2(n=(40, 36, 20), nsteps=10), (2, 0, 2),
+                                                 -1.5), FP64_TOL),
+    "c4_small_q-3_inflow_y": (lambda: _inflow(W.config4(n=(72, 40), nsteps=10), (0, 2), -3.0),
+                              FP64_TOL),
+    "c3_small_order2_kF_q-3": (lambda: _with_kF(W.config3(n=(48, 24, 20), nsteps=8,
+                                                          precision="fp64", kappa_T_power=-3.0)),
+                               FP64_TOL),
+    "c1_rk2ssp_q-1_inflow": (lambda: _inflow(W.config1(nsteps=300, scheme="rk2ssp"), (2,), -1.0),
+                             FP64_TOL),
+    "c5_small_q-3_inflow_mixed": (lambda: _inflow(W.config5(n=(36, 20, 18), nsteps=6), (2, 2, 2),
+                                                  -3.0), MIXED_TOL),
+    "c2_small_eps_inflow": (lambda: _inflow(W.config2(n=(40, 36, 20), nsteps=10, hll_eps_cells=2.0),
+                                            (2, 1, 2)), FP64_TOL),
+    "marshak_cfl10_300": (lambda: W.marshak(cfl=10.0, t_end=300 * 10.0 * 0.011 / W.MARSHAK["c"]),
+                          FP64_TOL),
+    "marshak_rk2ssp_cfl0.9_2000": (lambda: W.marshak(cfl=0.9, scheme="rk2ssp",
+                                                     t_end=2000 * 0.9 * 0.011 / W.MARSHAK["c"]),
+                                   FP64_TOL),
+}
+
+
+@pytest.mark.parametrize("case", sorted(STEP_CASES))
+def test_steps_with_inflow_and_temperature_dependent_opacity_match_oracle(torch_dev, orc, case):
+    mk, tol = STEP_CASES[case]
+    w = mk()
+    _say("steps", case, w.n, w.nsteps, w.params["precision"], w.params["bc"])
+    ref, st, _ = orc.step(w.params, w.y0, w.rho, w.kappa_P, w.kappa_F, w.dt, w.nsteps)
+    assert st == 0
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, w.y0)
+    S.step(yd, w.dt, w.nsteps)
+    err = _rel_err(yd.cpu().numpy(), ref, range(w.nvar))
+    _say("  max rel err per field", err)
+    assert err.max() < tol, err
+
+
+def test_marshak_wave_full_run(torch_dev, orc):
+    """5451 PD-ARS steps at CFL 10 to t = 2e-8 s: against the oracle's run, and
+    the gas temperature against the self-similar equilibrium-diffusion solution
+    (the same reference and bounds as the oracle's own pin)."""
+    from test_oracle_marshak import equilibrium_diffusion, _x_half, X, CV
+    w = W.marshak(cfl=10.0)
+    assert w.nsteps == 5451
+    _say("marshak full", w.nsteps)
+    ref, st, _ = orc.step(w.params, w.y0, w.rho, w.kappa_P, None, w.dt, w.nsteps)
+    assert st == 0
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, w.y0)
+    S.step(yd, w.dt, w.nsteps)
+    got = yd.cpu().numpy()
+    err = _rel_err(got, ref, range(w.nvar))
+    _say("  max rel err per field", err)
+    assert err.max() < FP64_TOL, err
+    Tfun, _ = equilibrium_diffusion(W.MARSHAK["t_end"])
+    Tref = Tfun(X)
+    T = got[2, 0, 0] / CV
+    assert np.abs(T - Tref).sum() / Tref.sum() < 0.03
+    assert abs(_x_half(T) - _x_half(Tref)) < 2 * (X[1] - X[0])

@@ -11,27 +11,15 @@ import numpy as np
 import pytest
 from scipy.integrate import solve_ivp
 
-K_PER_KEV = 1.160452e7
-A_R = 7.5657e-15 * K_PER_KEV ** 4        # erg cm^-3 keV^-4
-C_LIGHT = 2.99792458e10
-CV = 3e15                                 # erg cm^-3 keV^-1
-TB, T0 = 1.0, 1e-3
-N, L = 60, 0.66
+from paper_2404_08247_amd import workloads as W
+
+M = W.MARSHAK
+A_R = M["a_r"]                            # erg cm^-3 keV^-4
+C_LIGHT = M["c"]
+CV = M["cv"]                              # erg cm^-3 keV^-1
+TB, T0 = M["T_hot"], M["T_cold"]
+N, L = 60, M["length"]
 DX = L / N
-
-
-def marshak_params(scheme="pdars"):
-    return dict(ndim=1, n=(N,), dx=DX, c=C_LIGHT, chat=C_LIGHT, gamma=5.0 / 3.0, a_r=A_R,
-                kB_over_mu=CV * (2.0 / 3.0), bc=(2,), closure="eddington", v_order=1,
-                scheme=scheme, kappa_T_power=-3.0, inflow_E=A_R * TB ** 4, inflow_F=0.0,
-                newton_maxit=400, outer_maxit=10)
-
-
-def marshak_initial():
-    y = np.zeros((4, 1, 1, N))
-    y[0] = A_R * T0 ** 4
-    y[2] = CV * T0
-    return y, np.ones((1, 1, N)), np.full((1, 1, N), 300.0)
 
 
 def equilibrium_diffusion(t):
@@ -73,7 +61,7 @@ def equilibrium_diffusion(t):
     return T, etaf * scale
 
 
-T_END = 2e-8
+T_END = M["t_end"]
 X = (np.arange(N) + 0.5) * DX
 
 
@@ -85,10 +73,9 @@ def reference():
 
 
 def _run(orc, scheme, cfl):
-    p = marshak_params(scheme)
-    y, rho, kap = marshak_initial()
-    ns = int(round(T_END / (cfl * DX / C_LIGHT)))
-    yo, st, _ = orc.step(p, y, rho, kap, None, T_END / ns, ns)
+    w = W.marshak(N, cfl=cfl, scheme=scheme)
+    assert abs(w.dt * w.nsteps - T_END) < 1e-12 * T_END
+    yo, st, _ = orc.step(w.params, w.y0, w.rho, w.kappa_P, None, w.dt, w.nsteps)
     return yo, st
 
 
@@ -123,14 +110,12 @@ def test_rk2ssp_marshak_front_runs_about_twice_too_fast(orc, reference):
 
 def test_inflow_boundary_in_equilibrium_is_steady(orc):
     # the inflow state equal to a uniform interior state: nothing moves
-    p = marshak_params()
     Tu = 0.5
-    p["inflow_E"] = A_R * Tu ** 4
-    y = np.zeros((4, 1, 1, N))
+    w = W.marshak(N, inflow_E=A_R * Tu ** 4)
+    y = np.zeros_like(w.y0)
     y[0] = A_R * Tu ** 4
     y[2] = CV * Tu
-    yo, st, _ = orc.step(p, y, np.ones((1, 1, N)), np.full((1, 1, N), 300.0), None,
-                         DX / C_LIGHT, 20)
+    yo, st, _ = orc.step(w.params, y, w.rho, w.kappa_P, None, DX / C_LIGHT, 20)
     assert st == 0
     np.testing.assert_allclose(yo[0], y[0], rtol=1e-13)
     np.testing.assert_allclose(yo[2], y[2], rtol=1e-13)
