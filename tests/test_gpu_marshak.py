@@ -202,3 +202,37 @@ def test_marshak_wave_full_run(torch_dev, orc):
     T = got[2, 0, 0] / CV
     assert np.abs(T - Tref).sum() / Tref.sum() < 0.03
     assert abs(_x_half(T) - _x_half(Tref)) < 2 * (X[1] - X[0])
+
+
+@pytest.mark.parametrize("cfl", [0.9, 2.0, 5.0, 10.0, 20.0])
+def test_marshak_cfl_sweep_on_gpu(torch_dev, cfl):
+    """PD-ARS on the GPU from CFL 0.9 to 20 (60564 ... 2725 steps): the gas
+    temperature stays within 3 % (L1) of the self-similar solution and the
+    half-temperature point within 2 cells of it."""
+    from test_oracle_marshak import equilibrium_diffusion, _x_half, X, CV
+    w = W.marshak(cfl=cfl)
+    _say("marshak cfl", cfl, w.nsteps)
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, w.y0)
+    S.step(yd, w.dt, w.nsteps)
+    T = yd.cpu().numpy()[2, 0, 0] / CV
+    Tfun, _ = equilibrium_diffusion(W.MARSHAK["t_end"])
+    Tref = Tfun(X)
+    l1 = np.abs(T - Tref).sum() / Tref.sum()
+    dxh = _x_half(T) - _x_half(Tref)
+    _say("  L1 %.4f  x_half offset %.4f cm" % (l1, dxh))
+    assert l1 < 0.03, l1
+    assert abs(dxh) < 2 * (X[1] - X[0])
+
+
+def test_marshak_rk2ssp_front_on_gpu(torch_dev):
+    """The RK2-SSP comparator at CFL 0.9 runs its front about twice too far."""
+    from test_oracle_marshak import equilibrium_diffusion, _x_half, X, CV
+    w = W.marshak(cfl=0.9, scheme="rk2ssp")
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, w.y0)
+    S.step(yd, w.dt, w.nsteps)
+    Tfun, _ = equilibrium_diffusion(W.MARSHAK["t_end"])
+    ratio = _x_half(yd.cpu().numpy()[2, 0, 0] / CV) / _x_half(Tfun(X))
+    _say("  rk2ssp x_half ratio %.3f" % ratio)
+    assert 1.5 < ratio < 2.5, ratio
