@@ -205,7 +205,12 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
 // opacity (kP when it is not a separate field); Ssrc: the radiation source S of
 // eq. FGFR over this sub-step (0 when absent).
 //
-// TDEP: every absorption coefficient is chi_X = rho kappa_X T^q (q = kT_pow),
+// Two instantiations: SRC_LEAN, the common case, takes chi_E = chi_P, S = 0,
+// constant opacities and (at order 2) chi_F = chi_E, and ignores kE and Ssrc;
+// SRC_GEN handles a separate kappa_E, the source S, chi_F != chi_E at order 2 and
+// temperature-dependent opacities. The host picks SRC_LEAN only when it applies.
+//
+// Temperature-dependent opacities (SRC_GEN, kT_pow = q != 0): every absorption coefficient is chi_X = rho kappa_X T^q (q = kT_pow),
 // taken at the temperature of the current Newton iterate (the chi of eq. Rnew
 // are at t+1) and at the converged T for the flux update and the outer test.
 // All of A, B and C of E(E_gas, R) are linear in the chi, so only the R/(tau chat)
@@ -214,17 +219,23 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
 //   E = (A + C - g R/(tau chat)) / B,  dF_R/dR = -g/(tau chat chi_E) - 1,
 // while dF_R/dE_gas keeps the ratio chi_P/chi_E, which T^q leaves unchanged (the
 // simplified Jacobian carries no d chi/dT).
-template <int ND, bool TDEP = false>
+enum SourceVariant : int { SRC_LEAN = 0, SRC_GEN = 1 };
+
+template <int ND, int SV>
 __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double& Eg, double* Pm,
-                                double rho, double kP, double kF, double kE, double Ssrc,
+                                double rho, double kP, double kF, double kE_in, double S_in,
                                 double tau, double inv_tch) {
+  constexpr bool GEN = (SV == SRC_GEN);
+  const double kE = GEN ? kE_in : kP;
+  const double Ssrc = GEN ? S_in : 0.0;
+  const bool tdep = GEN && P.kT_pow != 0.0;   // uniform over the launch
   double chiP = rho * kP;
   double chiE = rho * kE;
   double chiF = rho * kF;
-  // field values (the pass coefficients below); chiP/E/F follow T when TDEP
+  // field values (the pass coefficients below); chiP/E/F follow T when tdep
   const double chiP0 = chiP, chiE0 = chiE, chiF0 = chiF;
   if (chiP == 0.0 && chiE == 0.0 && chiF == 0.0) {   // no coupling: E += S only
-    E += Ssrc;
+    if constexpr (GEN) E += Ssrc;
     return 0u;
   }
   const double ch = P.chat;
@@ -251,12 +262,14 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   double Eb = E0;
   double Egas = Eg0;
   double R = 0.0;
-  const double tol = P.newton_rtol * (Eg0 + k_cc * (E0 + Ssrc));
+  // (x + 0 is not folded away, since it maps -0 to +0: the lean path skips the
+  // S terms explicitly)
+  const double tol = P.newton_rtol * (Eg0 + k_cc * (GEN ? E0 + Ssrc : E0));
   // simplified Jacobian (fixed for the call): dF_R/dR and the T^3 factor of
   // dF_R/dE_gas = (1/C_v) d/dT (chi_P/chi_E a T^4)
   const double J22c = -inv_tch * inv_chiE;
   const double J22 = J22c - 1.0;
-  const double J21c = 4.0 * ar * inv_Cv * (kP == kE ? 1.0 : chiP * inv_chiE);
+  const double J21c = 4.0 * ar * inv_Cv * ((!GEN || kP == kE) ? 1.0 : chiP * inv_chiE);
   const double ctau = ch * tau;
   // order 1: 1/B = 1/chi_E and the flux denominator do not change between passes
   const double inv_den_o1 = o2 ? 0.0 : rcp(1.0 + ctau * chiF);
@@ -284,7 +297,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     if (o2) {
       const double a1 = 1.0 + 0.5 * b2;
       a2 = 1.0 + ctau * chiF0 * a1;
-      if (chiF0 == chiE0) {
+      if (!GEN || chiF0 == chiE0) {
         const double q = rcp(a1 * a2);
         inv_B = q * a2 * inv_chiE;
         inv_den = q * a1;
@@ -304,17 +317,17 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     for (int it = 0;; ++it) {
       const double T = (Egas - KE) * inv_Cv;
       const double T2 = T * T;
-      const double gT = TDEP ? pow(T, -P.kT_pow) : 1.0;   // chi(field) / chi(T)
+      const double gT = tdep ? pow(T, -P.kT_pow) : 1.0;   // chi(field) / chi(T)
       const double Er = (Aco * T2 * T2 + Cc - R * inv_tch * gT) * inv_B;
       const double FG = Egas - Eg0 + k_cc * R;
-      const double FR = Er - E0 - (R + Ssrc);
+      const double FR = Er - E0 - (GEN ? R + Ssrc : R);
       if (fabs(FG) < tol && k_cc * fabs(FR) < tol) {
         conv = true;
         break;
       }
       if (it >= P.newton_maxit) break;
       const double J21 = J21c * T2 * T;
-      const double J22t = TDEP ? J22c * gT - 1.0 : J22;
+      const double J22t = tdep ? J22c * gT - 1.0 : J22;
       const double inv_det = rcp1(J22t - k_cc * J21);
       Egas += (k_cc * FR - J22t * FG) * inv_det;
       R += (J21 * FG - FR) * inv_det;
@@ -331,9 +344,10 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     //   rhs = F(t) + chat tau [chi_P a T^4 v + chi_F E D v + (chi_F - chi_E) E v],
     // solved by Sherman-Morrison: F = (rhs - b v (v.rhs)/(a + b v^2))/a (eq. numF2
     // when chi_F = chi_E).
-    Enew = E0 - P.chat_over_c * (Egas - Eg0) + Ssrc;
+    Enew = E0 - P.chat_over_c * (Egas - Eg0);
+    if constexpr (GEN) Enew += Ssrc;
     const double Tn = (Egas - KE) * inv_Cv;
-    if constexpr (TDEP) {   // absorption at the converged T for the flux and the outer test
+    if (tdep) {   // absorption at the converged T for the flux and the outer test
       const double fT = pow(Tn, P.kT_pow);
       chiP = chiP0 * fT;
       chiE = chiE0 * fT;
@@ -358,14 +372,14 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       vr += v[k] * rhs[k];
     }
     double corr = 0.0;   // b (v.rhs)/(a + b v^2)
-    if (o2 && chiF != chiE) {
+    if (GEN && o2 && chiF != chiE) {
       const double bb = 2.0 * ctau * (chiF - chiE) * P.inv_c2;
       corr = bb * vr * rcp(a2 + bb * v2);
     }
     double v2n = 0.0, wF_new = 0.0, Fv_new = 0.0;
 #pragma unroll
     for (int k = 0; k < ND; ++k) {
-      const double Fn = (rhs[k] - corr * v[k]) * inv_den;
+      const double Fn = (GEN ? rhs[k] - corr * v[k] : rhs[k]) * inv_den;
       const double vn = (P0[k] - (Fn - F0[k]) * P.inv_c_chat) * inv_rho;
       v2n += vn * vn;
       wF_new += vn * Fn;

@@ -81,10 +81,12 @@ __device__ __forceinline__ double inflow_value(const DevParams& P, int r, int ax
 }
 
 // Kernel variants (separate instantiations, so the plain path carries none of
-// their code): VAR_EPS, the optional Skinner-type eps on the HLL energy flux,
-// which stages chi_F = rho kappa_F of the tile in LDS; VAR_TDEP, opacities that
-// follow the temperature in the local source.
-enum { VAR_PLAIN = 0, VAR_EPS = 1, VAR_TDEP = 2 };
+// their code): VAR_PLAIN, plain HLL with the lean local source; VAR_GEN, plain
+// HLL with the general source (a separate kappa_E, the source S, chi_F != chi_E
+// at order 2, temperature-dependent opacities); VAR_EPS, the optional
+// Skinner-type eps on the HLL energy flux, which stages chi_F = rho kappa_F of the
+// tile in LDS, with the general source.
+enum { VAR_PLAIN = 0, VAR_EPS = 1, VAR_GEN = 2 };
 
 template <int ND, int MODE, typename TT, int VAR>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(RHD_STAGE_WAVES)))
@@ -92,7 +94,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
         const double* __restrict__ rho, const double* __restrict__ kP,
         const double* __restrict__ kF, double dt, int zchunk, unsigned long long* err) {
   constexpr bool EPS = (VAR == VAR_EPS);
-  constexpr bool TDEP = (VAR == VAR_TDEP);
+  constexpr int SV = (VAR == VAR_PLAIN) ? SRC_LEAN : SRC_GEN;
   constexpr int TX = TileShape<ND>::TX;
   constexpr int TY = TileShape<ND>::TY;
   constexpr int NR = 1 + ND;                 // radiation variables E, F_1..F_ND
@@ -226,6 +228,9 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
   int htile = 0;
   bool hfx = false, hfy = false;
   int hfix = -1;   // axis whose inflow state this halo position holds (-1: none)
+  // some halo position of this workgroup lies below an inflow axis (uniform)
+  const bool inflow_blk = (x0 < HALO && P.bc[0] == BC_INFLOW) ||
+                          (ND >= 2 && y0 < HALO && P.bc[1] == BC_INFLOW);
   if (tid < NHX + NHY) {
     int lx, ly;
     if (tid < NHX) {
@@ -286,8 +291,10 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       pre_rho = rho[qc];
       pre_kp = kP[qc];
       pre_kf = P.kF_alias ? pre_kp : kF[qc];
-      pre_ke = P.kE ? P.kE[qc] : pre_kp;
-      if (P.jS) pre_j = P.jS[qc];
+      if constexpr (SV == SRC_GEN) {
+        pre_ke = P.kE ? P.kE[qc] : pre_kp;
+        if (P.jS) pre_j = P.jS[qc];
+      }
     }
     // ---------------- stage the plane's (E, F) tile in LDS ----------------
     double own[NR];
@@ -311,8 +318,13 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
     if (hoff >= 0) {
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        s_area[r][htile] = hfix >= 0 ? inflow_value(P, r, hfix)
-                                     : (((hfx && r == 1) || (hfy && r == 2)) ? -hv[r] : hv[r]);
+        s_area[r][htile] = ((hfx && r == 1) || (hfy && r == 2)) ? -hv[r] : hv[r];
+      // below an inflow axis the fixed state replaces the loaded value (same
+      // thread, same address: program order)
+      if (inflow_blk && hfix >= 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) s_area[r][htile] = inflow_value(P, r, hfix);
+      }
     }
     double chi_k = 0.0, chi_k1 = 0.0;   // chi_F of the own cell at planes k and k+1 (EPS)
     if constexpr (EPS) {
@@ -511,8 +523,8 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       // of the step with the full dt
       const unsigned st = (MODE == MODE_STAGE1 && P.scheme == 1)
                               ? 0u
-                              : source_cell<ND, TDEP>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, pre_ke,
-                                                      pre_j * tau_src, tau_src, inv_tch);
+                              : source_cell<ND, SV>(P, E, F, Eg, Pm, pre_rho, pre_kp, pre_kf, pre_ke,
+                                                    pre_j * tau_src, tau_src, inv_tch);
       if (st) report(err, q, st);
       yw[q] = E;
 #pragma unroll
@@ -525,7 +537,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
 }
 
 // Source only (no transport), one cell per thread.
-template <int ND, bool TDEP>
+template <int ND, int SV>
 __global__ void __launch_bounds__(NTHREADS)
 k_source(DevParams P, double* y, const double* __restrict__ rho, const double* __restrict__ kP,
          const double* __restrict__ kF, double tau, unsigned long long* err) {
@@ -539,9 +551,9 @@ k_source(DevParams P, double* y, const double* __restrict__ rho, const double* _
     Pm[k] = y[(2 + ND + k) * N + q];
   }
   const double kp = kP[q];
-  const unsigned st = source_cell<ND, TDEP>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q],
-                                           P.kE ? P.kE[q] : kp, P.jS ? P.jS[q] * tau : 0.0, tau,
-                                           rcp(tau * P.chat));
+  const unsigned st = source_cell<ND, SV>(P, E, F, Eg, Pm, rho[q], kp, P.kF_alias ? kp : kF[q],
+                                         P.kE ? P.kE[q] : kp, P.jS ? P.jS[q] * tau : 0.0, tau,
+                                         rcp(tau * P.chat));
   if (st) report(err, q, st);
   y[q] = E;
   y[(1 + ND) * N + q] = Eg;
@@ -594,6 +606,11 @@ k_totals(DevParams P, const double* __restrict__ y, double* __restrict__ partial
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// The lean source applies unless one of its assumptions fails.
+static bool needs_general_source(const DevParams& P) {
+  return P.kE != nullptr || P.jS != nullptr || P.kT_pow != 0.0 || (P.v_order == 2 && !P.kF_alias);
+}
+
 template <int ND, int MODE, typename TT, int VAR>
 static hipError_t launch_nd(const DevParams& P, const double* ys, const double* yo, double* yw,
                             const double* rho, const double* kP, const double* kF, double dt,
@@ -619,20 +636,20 @@ template <int MODE, typename TT>
 static hipError_t launch_mode(const DevParams& P, const double* ys, const double* yo, double* yw,
                               const double* rho, const double* kP, const double* kF, double dt,
                               unsigned long long* err, hipStream_t s) {
-  // the host rejects eps together with temperature-dependent opacities; the
-  // transport-only mode runs no source, so it never needs VAR_TDEP
+  // the transport-only mode runs no source, so it never needs VAR_GEN
   const int var = P.eps_dx > 0.0 ? VAR_EPS
-                                 : ((P.kT_pow != 0.0 && MODE != MODE_TRANSPORT) ? VAR_TDEP : VAR_PLAIN);
+                                 : ((MODE != MODE_TRANSPORT && needs_general_source(P)) ? VAR_GEN
+                                                                                        : VAR_PLAIN);
   switch (P.ndim * 4 + var) {
     case 4 + VAR_PLAIN: return launch_nd<1, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 4 + VAR_EPS: return launch_nd<1, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
-    case 4 + VAR_TDEP: return launch_nd<1, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 4 + VAR_GEN: return launch_nd<1, MODE, TT, VAR_GEN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 8 + VAR_PLAIN: return launch_nd<2, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 8 + VAR_EPS: return launch_nd<2, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
-    case 8 + VAR_TDEP: return launch_nd<2, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 8 + VAR_GEN: return launch_nd<2, MODE, TT, VAR_GEN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 12 + VAR_PLAIN: return launch_nd<3, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 12 + VAR_EPS: return launch_nd<3, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
-    case 12 + VAR_TDEP: return launch_nd<3, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 12 + VAR_GEN: return launch_nd<3, MODE, TT, VAR_GEN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -657,14 +674,14 @@ hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* 
 hipError_t launch_source(const DevParams& P, double* y, const double* rho, const double* kP,
                          const double* kF, double tau, unsigned long long* err, hipStream_t s) {
   const unsigned blocks = (unsigned)((P.N + NTHREADS - 1) / NTHREADS);
-  const bool tdep = P.kT_pow != 0.0;
-  switch (P.ndim * 2 + (tdep ? 1 : 0)) {
-    case 2: hipLaunchKernelGGL((k_source<1, false>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 3: hipLaunchKernelGGL((k_source<1, true>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 4: hipLaunchKernelGGL((k_source<2, false>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 5: hipLaunchKernelGGL((k_source<2, true>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 6: hipLaunchKernelGGL((k_source<3, false>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 7: hipLaunchKernelGGL((k_source<3, true>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+  const int sv = needs_general_source(P) ? SRC_GEN : SRC_LEAN;
+  switch (P.ndim * 2 + sv) {
+    case 2: hipLaunchKernelGGL((k_source<1, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 3: hipLaunchKernelGGL((k_source<1, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 4: hipLaunchKernelGGL((k_source<2, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 5: hipLaunchKernelGGL((k_source<2, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 6: hipLaunchKernelGGL((k_source<3, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 7: hipLaunchKernelGGL((k_source<3, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
