@@ -102,6 +102,55 @@ def bench_mixed(torch, rhd, W, dev, to):
     return out
 
 
+def bench_options(torch, rhd, W, dev, to, nsteps=50):
+    """The same 128^3 FP64 workload with each optional part of the step switched on
+    (one at a time), and the Marshak wave (60 cells, 5451 steps at CFL 10): rate
+    and time per step, and the ratio to the plain step's time."""
+    base = W.config2(precision="fp64")
+    rng = np.random.default_rng(77)
+    kE = base.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, base.kappa_P.shape)
+    kF = base.kappa_P * 10.0 ** rng.uniform(-0.5, 0.5, base.kappa_P.shape)
+    jS = rng.uniform(0.0, 0.1, base.kappa_P.shape) * base.y0[0] / (200 * base.dt)
+    Ein = 2.0 * base.y0[0].max()
+    inflow = dict(bc=(2, 0, 0), inflow_E=Ein, inflow_F=0.3 * Ein)
+    cases = {
+        "plain": ({}, None, False),
+        "rk2ssp": ({"scheme": "rk2ssp"}, None, False),
+        "hll_eps_2cells": ({"hll_eps_cells": 2.0}, None, False),
+        "kappa_F_order2": ({}, kF, False),
+        "kappa_E_and_source": ({}, None, True),
+        "T_pow_-3_inflow_x": (dict(kappa_T_power=-3.0, newton_maxit=400, **inflow), None, False),
+    }
+    out = {"workload": f"3-D 128^3 static mixed-regime grid, FP64, {nsteps} steps per option"}
+    t_plain = None
+    for name, (over, kf, kes) in cases.items():
+        p = dict(base.params, **over)
+        S = rhd.Solver(p, to(base.rho), to(base.kappa_P), None if kf is None else to(kf), 0, dev)
+        if kes:
+            kEd, jd = to(kE), to(jS)
+            S.set_kappa_E(kEd)
+            S.set_radiation_source(jd)
+        y = to(base.y0)
+        S.step(y, base.dt, 3)
+        dt_s = _timed(torch, lambda: S.step(y, base.dt, nsteps))
+        if t_plain is None:
+            t_plain = dt_s
+        out[name] = {"value": base.ncells * nsteps / dt_s, "unit": "cell-updates/s",
+                     "ms_per_step": dt_s / nsteps * 1e3, "time_vs_plain": dt_s / t_plain}
+        print(f"[bench] option {name}: {dt_s / nsteps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+        del S
+    w = W.marshak(cfl=10.0)
+    S = rhd.Solver(w.params, to(w.rho), to(w.kappa_P), None, 0, dev)
+    y = to(w.y0)
+    S.step(y, w.dt, 10)
+    y = to(w.y0)
+    dt_s = _timed(torch, lambda: S.step(y, w.dt, w.nsteps))
+    out["marshak_60_cfl10"] = {"steps": w.nsteps, "seconds": dt_s,
+                               "us_per_step": dt_s / w.nsteps * 1e6}
+    print(f"[bench] marshak: {dt_s:.3f} s for {w.nsteps} steps", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_adjoint(torch, rhd, W, dev, to):
     """2-D 512^2 adjoint workload (200 steps, checkpoints every 20): forward with
     checkpoint copies, then the full backward (recompute + reverse of every
@@ -208,6 +257,7 @@ def main():
     if not args.no_extras:
         extras["mixed_vs_fp64"] = bench_mixed(torch, rhd, W, dev, to)
         extras["adjoint"] = bench_adjoint(torch, rhd, W, dev, to)
+        extras["options"] = bench_options(torch, rhd, W, dev, to)
 
     cpu = None
     if args.cpu_steps > 0:

@@ -149,6 +149,8 @@ rhd::DevParams make_dev(const rhd_params* p, bool alias) {
   d.scheme = p->scheme;
   d.eps_dx = p->hll_eps_cells * p->dx;
   d.kT_pow = p->kappa_T_power;
+  d.kT_isint = (p->kappa_T_power == std::nearbyint(p->kappa_T_power) && std::fabs(p->kappa_T_power) <= 16.0);
+  d.kT_int = d.kT_isint ? (int)p->kappa_T_power : 0;
   d.inflow_E = p->inflow_E;
   d.inflow_F = p->inflow_F;
   return d;

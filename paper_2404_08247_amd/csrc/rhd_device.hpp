@@ -205,12 +205,13 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
 // opacity (kP when it is not a separate field); Ssrc: the radiation source S of
 // eq. FGFR over this sub-step (0 when absent).
 //
-// Two instantiations: SRC_LEAN, the common case, takes chi_E = chi_P, S = 0,
+// Three instantiations: SRC_LEAN, the common case, takes chi_E = chi_P, S = 0,
 // constant opacities and (at order 2) chi_F = chi_E, and ignores kE and Ssrc;
-// SRC_GEN handles a separate kappa_E, the source S, chi_F != chi_E at order 2 and
-// temperature-dependent opacities. The host picks SRC_LEAN only when it applies.
+// SRC_GEN handles a separate kappa_E, the source S and chi_F != chi_E at order 2;
+// SRC_TDEP adds temperature-dependent opacities. The host picks the leanest one
+// that applies (each extra costs registers in the whole stage kernel).
 //
-// Temperature-dependent opacities (SRC_GEN, kT_pow = q != 0): every absorption coefficient is chi_X = rho kappa_X T^q (q = kT_pow),
+// Temperature-dependent opacities (SRC_TDEP, kT_pow = q != 0): every absorption coefficient is chi_X = rho kappa_X T^q (q = kT_pow),
 // taken at the temperature of the current Newton iterate (the chi of eq. Rnew
 // are at t+1) and at the converged T for the flux update and the outer test.
 // All of A, B and C of E(E_gas, R) are linear in the chi, so only the R/(tau chat)
@@ -219,16 +220,33 @@ __device__ __forceinline__ void closure_ig(int closure, double c, double E, doub
 //   E = (A + C - g R/(tau chat)) / B,  dF_R/dR = -g/(tau chat chi_E) - 1,
 // while dF_R/dE_gas keeps the ratio chi_P/chi_E, which T^q leaves unchanged (the
 // simplified Jacobian carries no d chi/dT).
-enum SourceVariant : int { SRC_LEAN = 0, SRC_GEN = 1 };
+enum SourceVariant : int { SRC_LEAN = 0, SRC_GEN = 1, SRC_TDEP = 2 };
+
+// x^n for an integer n that is uniform over the launch (binary powering)
+__device__ __forceinline__ double ipow(double x, int n) {
+  unsigned m = n < 0 ? 0u - (unsigned)n : (unsigned)n;
+  double r = 1.0, b = x;
+  while (m) {
+    if (m & 1u) r *= b;
+    b *= b;
+    m >>= 1;
+  }
+  return n < 0 ? rcp(r) : r;
+}
+
+// T^(s q) for s = +1 or -1: repeated products when q is a small integer, else pow
+__device__ __forceinline__ double opacity_tpow(const DevParams& P, double T, int s) {
+  return P.kT_isint ? ipow(T, s * P.kT_int) : pow(T, s * P.kT_pow);
+}
 
 template <int ND, int SV>
 __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double& Eg, double* Pm,
                                 double rho, double kP, double kF, double kE_in, double S_in,
                                 double tau, double inv_tch) {
-  constexpr bool GEN = (SV == SRC_GEN);
+  constexpr bool GEN = (SV >= SRC_GEN);
+  constexpr bool tdep = (SV == SRC_TDEP);
   const double kE = GEN ? kE_in : kP;
   const double Ssrc = GEN ? S_in : 0.0;
-  const bool tdep = GEN && P.kT_pow != 0.0;   // uniform over the launch
   double chiP = rho * kP;
   double chiE = rho * kE;
   double chiF = rho * kF;
@@ -317,7 +335,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     for (int it = 0;; ++it) {
       const double T = (Egas - KE) * inv_Cv;
       const double T2 = T * T;
-      const double gT = tdep ? pow(T, -P.kT_pow) : 1.0;   // chi(field) / chi(T)
+      const double gT = tdep ? opacity_tpow(P, T, -1) : 1.0;   // chi(field) / chi(T)
       const double Er = (Aco * T2 * T2 + Cc - R * inv_tch * gT) * inv_B;
       const double FG = Egas - Eg0 + k_cc * R;
       const double FR = Er - E0 - (GEN ? R + Ssrc : R);
@@ -347,8 +365,8 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     Enew = E0 - P.chat_over_c * (Egas - Eg0);
     if constexpr (GEN) Enew += Ssrc;
     const double Tn = (Egas - KE) * inv_Cv;
-    if (tdep) {   // absorption at the converged T for the flux and the outer test
-      const double fT = pow(Tn, P.kT_pow);
+    if constexpr (tdep) {   // absorption at the converged T for the flux and the outer test
+      const double fT = opacity_tpow(P, Tn, 1);
       chiP = chiP0 * fT;
       chiE = chiE0 * fT;
       chiF = chiF0 * fT;

@@ -83,10 +83,10 @@ __device__ __forceinline__ double inflow_value(const DevParams& P, int r, int ax
 // Kernel variants (separate instantiations, so the plain path carries none of
 // their code): VAR_PLAIN, plain HLL with the lean local source; VAR_GEN, plain
 // HLL with the general source (a separate kappa_E, the source S, chi_F != chi_E
-// at order 2, temperature-dependent opacities); VAR_EPS, the optional
-// Skinner-type eps on the HLL energy flux, which stages chi_F = rho kappa_F of the
-// tile in LDS, with the general source.
-enum { VAR_PLAIN = 0, VAR_EPS = 1, VAR_GEN = 2 };
+// at order 2); VAR_TDEP, the general source with temperature-dependent
+// opacities; VAR_EPS, the optional Skinner-type eps on the HLL energy flux, which
+// stages chi_F = rho kappa_F of the tile in LDS, with the general source.
+enum { VAR_PLAIN = 0, VAR_EPS = 1, VAR_GEN = 2, VAR_TDEP = 3 };
 
 template <int ND, int MODE, typename TT, int VAR>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(RHD_STAGE_WAVES)))
@@ -94,7 +94,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
         const double* __restrict__ rho, const double* __restrict__ kP,
         const double* __restrict__ kF, double dt, int zchunk, unsigned long long* err) {
   constexpr bool EPS = (VAR == VAR_EPS);
-  constexpr int SV = (VAR == VAR_PLAIN) ? SRC_LEAN : SRC_GEN;
+  constexpr int SV = (VAR == VAR_PLAIN) ? SRC_LEAN : (VAR == VAR_TDEP ? SRC_TDEP : SRC_GEN);
   constexpr int TX = TileShape<ND>::TX;
   constexpr int TY = TileShape<ND>::TY;
   constexpr int NR = 1 + ND;                 // radiation variables E, F_1..F_ND
@@ -291,7 +291,7 @@ k_stage(DevParams P, const double* __restrict__ ys, const double* yo, double* yw
       pre_rho = rho[qc];
       pre_kp = kP[qc];
       pre_kf = P.kF_alias ? pre_kp : kF[qc];
-      if constexpr (SV == SRC_GEN) {
+      if constexpr (SV >= SRC_GEN) {
         pre_ke = P.kE ? P.kE[qc] : pre_kp;
         if (P.jS) pre_j = P.jS[qc];
       }
@@ -606,9 +606,11 @@ k_totals(DevParams P, const double* __restrict__ y, double* __restrict__ partial
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-// The lean source applies unless one of its assumptions fails.
-static bool needs_general_source(const DevParams& P) {
-  return P.kE != nullptr || P.jS != nullptr || P.kT_pow != 0.0 || (P.v_order == 2 && !P.kF_alias);
+// The leanest source instantiation whose assumptions hold.
+static int source_variant(const DevParams& P) {
+  if (P.kT_pow != 0.0) return SRC_TDEP;
+  if (P.kE != nullptr || P.jS != nullptr || (P.v_order == 2 && !P.kF_alias)) return SRC_GEN;
+  return SRC_LEAN;
 }
 
 template <int ND, int MODE, typename TT, int VAR>
@@ -636,20 +638,24 @@ template <int MODE, typename TT>
 static hipError_t launch_mode(const DevParams& P, const double* ys, const double* yo, double* yw,
                               const double* rho, const double* kP, const double* kF, double dt,
                               unsigned long long* err, hipStream_t s) {
-  // the transport-only mode runs no source, so it never needs VAR_GEN
+  // the transport-only mode runs no source, so it needs neither VAR_GEN nor
+  // VAR_TDEP; the host rejects eps together with T-dependent opacities
+  const int sv = (MODE == MODE_TRANSPORT) ? SRC_LEAN : source_variant(P);
   const int var = P.eps_dx > 0.0 ? VAR_EPS
-                                 : ((MODE != MODE_TRANSPORT && needs_general_source(P)) ? VAR_GEN
-                                                                                        : VAR_PLAIN);
+                                 : (sv == SRC_TDEP ? VAR_TDEP : (sv == SRC_GEN ? VAR_GEN : VAR_PLAIN));
   switch (P.ndim * 4 + var) {
     case 4 + VAR_PLAIN: return launch_nd<1, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 4 + VAR_EPS: return launch_nd<1, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 4 + VAR_GEN: return launch_nd<1, MODE, TT, VAR_GEN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 4 + VAR_TDEP: return launch_nd<1, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 8 + VAR_PLAIN: return launch_nd<2, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 8 + VAR_EPS: return launch_nd<2, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 8 + VAR_GEN: return launch_nd<2, MODE, TT, VAR_GEN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 8 + VAR_TDEP: return launch_nd<2, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 12 + VAR_PLAIN: return launch_nd<3, MODE, TT, VAR_PLAIN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 12 + VAR_EPS: return launch_nd<3, MODE, TT, VAR_EPS>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     case 12 + VAR_GEN: return launch_nd<3, MODE, TT, VAR_GEN>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
+    case 12 + VAR_TDEP: return launch_nd<3, MODE, TT, VAR_TDEP>(P, ys, yo, yw, rho, kP, kF, dt, err, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -674,14 +680,17 @@ hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* 
 hipError_t launch_source(const DevParams& P, double* y, const double* rho, const double* kP,
                          const double* kF, double tau, unsigned long long* err, hipStream_t s) {
   const unsigned blocks = (unsigned)((P.N + NTHREADS - 1) / NTHREADS);
-  const int sv = needs_general_source(P) ? SRC_GEN : SRC_LEAN;
-  switch (P.ndim * 2 + sv) {
-    case 2: hipLaunchKernelGGL((k_source<1, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 3: hipLaunchKernelGGL((k_source<1, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 4: hipLaunchKernelGGL((k_source<2, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 5: hipLaunchKernelGGL((k_source<2, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 6: hipLaunchKernelGGL((k_source<3, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
-    case 7: hipLaunchKernelGGL((k_source<3, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+  const int sv = source_variant(P);
+  switch (P.ndim * 3 + sv) {
+    case 3: hipLaunchKernelGGL((k_source<1, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 4: hipLaunchKernelGGL((k_source<1, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 5: hipLaunchKernelGGL((k_source<1, SRC_TDEP>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 6: hipLaunchKernelGGL((k_source<2, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 7: hipLaunchKernelGGL((k_source<2, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 8: hipLaunchKernelGGL((k_source<2, SRC_TDEP>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 9: hipLaunchKernelGGL((k_source<3, SRC_LEAN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 10: hipLaunchKernelGGL((k_source<3, SRC_GEN>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
+    case 11: hipLaunchKernelGGL((k_source<3, SRC_TDEP>), dim3(blocks), dim3(NTHREADS), 0, s, P, y, rho, kP, kF, tau, err); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -29,6 +29,7 @@ struct DevParams {
   int scheme;         // 0 PD-ARS, 1 RK2-SSP comparator
   double eps_dx;      // hll_eps_cells * dx (0: plain HLL)
   double kT_pow;      // opacity temperature exponent (0: constant opacities)
+  int kT_isint, kT_int;   // kT_pow is the integer kT_int (|kT_int| <= 16)
   double inflow_E, inflow_F;   // ghost state of RHD_BC_INFLOW axes
   const double* kE;   // energy-mean opacity per unit mass (device), or null: kappa_P
   const double* jS;   // radiation injection rate per unit volume (device), or null: none
