@@ -84,6 +84,15 @@ def lib():
         L.oracle_step_dual.argtypes = [pp, dp, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double,
                                        ctypes.c_int, i64p]
         L.oracle_step_dual.restype = ctypes.c_int
+        L.oracle_hydro_step.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_int, i64p]
+        L.oracle_hydro_step.restype = ctypes.c_int
+        L.oracle_hydro_rhs.argtypes = [pp, dp, dp, dp, dp]
+        L.oracle_hydro_rhs.restype = None
+        L.oracle_hllc.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.oracle_hllc.restype = None
+        L.oracle_rhd_step.argtypes = [pp, dp, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, i64p]
+        L.oracle_rhd_step.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -221,6 +230,49 @@ def step_dual(p: dict, y, ty, rho, kP, tkP, kF, tkF, dt: float, nsteps: int, kE=
                                 _dp(tkP), _dp(kF), _dp(tkF), _dp(kE), _dp(jS), float(dt),
                                 int(nsteps), ctypes.byref(fc))
     return y, ty, st, fc.value
+
+
+def hydro_step(p: dict, y: np.ndarray, rho, dt: float, nsteps: int = 1):
+    """nsteps RK2-SSP hydro steps (PPM + HLLC) of rho and of y's E_gas and
+    momentum rows. Returns (y_new, rho_new, status, fail_cell)."""
+    y = np.array(y, dtype=np.float64, order="C", copy=True)
+    rho = np.array(rho, dtype=np.float64, order="C", copy=True)
+    fc = ctypes.c_int64(-1)
+    st = lib().oracle_hydro_step(ctypes.byref(make_params(p)), _dp(y), _dp(rho), float(dt),
+                                 int(nsteps), ctypes.byref(fc))
+    return y, rho, st, fc.value
+
+
+def hydro_rhs(p: dict, y: np.ndarray, rho):
+    """L(U) of the gas: (d rho/dt, d y/dt) with only the E_gas and momentum rows
+    of the latter nonzero."""
+    y, rho = _c(y), _c(rho)
+    srho = np.zeros_like(rho)
+    sy = np.zeros_like(y)
+    lib().oracle_hydro_rhs(ctypes.byref(make_params(p)), _dp(y), _dp(rho), _dp(srho), _dp(sy))
+    return srho, sy
+
+
+def hllc(gamma: float, nd: int, d: int, WL, WR) -> np.ndarray:
+    """HLLC flux along axis d between primitive states (rho, v_0..v_{nd-1}, p)."""
+    WL, WR = _c(WL), _c(WR)
+    out = np.zeros(2 + nd)
+    lib().oracle_hllc(float(gamma), int(nd), int(d), _dp(WL), _dp(WR), _dp(out))
+    return out
+
+
+def rhd_step(p: dict, y: np.ndarray, rho, kP, kF, dt: float, nsub: int, nsteps: int, kE=None,
+             jS=None):
+    """Operator-split steps: each is one hydro step of dt, then nsub radiation
+    steps of dt / nsub. Returns (y_new, rho_new, status, fail_cell)."""
+    y = np.array(y, dtype=np.float64, order="C", copy=True)
+    rho = np.array(rho, dtype=np.float64, order="C", copy=True)
+    kP, kF, kE, jS = _c(kP), _c(kF), _c(kE), _c(jS)
+    fc = ctypes.c_int64(-1)
+    st = lib().oracle_rhd_step(ctypes.byref(make_params(p)), _dp(y), _dp(rho), _dp(kP), _dp(kF),
+                               _dp(kE), _dp(jS), float(dt), int(nsub), int(nsteps),
+                               ctypes.byref(fc))
+    return y, rho, st, fc.value
 
 
 def num_threads() -> int:

@@ -28,6 +28,9 @@
 //              Jacobian, the E_tot convergence test, energy recovery from
 //              conservation, flux update eq. (numF1)/(numF2), momentum update,
 //              and the outer iteration over lagged v and F.
+//   hydro      Sec. 3.1: the explicit hydrodynamics step of the operator split
+//              (PPM + HLLC, RK2-SSP), and the split step: one hydro step, then
+//              the radiation subcycled over it.
 //
 // Readings of points the paper leaves open or prints inconsistently are listed
 // next to the code that takes them.
@@ -694,6 +697,181 @@ static void pdars_step(const oracle_params* p, const Grid& g, S* y, const S* rho
 }
 
 // ---------------------------------------------------------------------------
+// Hydrodynamics: the explicit first half of the operator split of Sec. 3.1, the
+// Euler equations for U = (rho, rho v, E_gas) with the ideal-gas pressure
+// p = (gamma - 1)(E_gas - rho |v|^2 / 2). The paper leaves the hydro scheme open
+// and integrates it in time with RK2-SSP; here, as a method of lines:
+//   edge states   PPM of the primitive variables (rho, v, p), the same
+//                 reconstruction as the radiation transport above;
+//   fluxes        HLLC (Toro, "Riemann Solvers and Numerical Methods for Fluid
+//                 Dynamics", 3rd ed., Sec. 10.4) with the wave-speed bounds
+//                 S_L = min(u_L - a_L, u_R - a_R), S_R = max(u_L + a_L, u_R + a_R);
+//   time          RK2-SSP (Shu & Osher 1988): U1 = U + dt L(U),
+//                 U^{n+1} = (U + U1 + dt L(U1)) / 2.
+// Ghost cells: periodic wrap, or a mirror with the normal velocity negated
+// (bc 1 and, for the gas, bc 2).
+// ---------------------------------------------------------------------------
+// Physical flux along d of the primitive state W = (rho, v_0..v_{nd-1}, p):
+// (rho u, rho u v_k + p delta_kd, (E + p) u), u = v_d.
+template <class S>
+static void euler_flux(double gamma, int nd, int d, const S* W, const S* U, S* f) {
+  const S u = W[1 + d];
+  f[0] = W[0] * u;
+  for (int k = 0; k < nd; ++k) f[1 + k] = U[1 + k] * u + (k == d ? W[1 + nd] : S(0.0));
+  f[1 + nd] = (U[1 + nd] + W[1 + nd]) * u;
+}
+
+template <class S>
+static void prim_to_cons(double gamma, int nd, const S* W, S* U) {
+  U[0] = W[0];
+  S v2 = S(0.0);
+  for (int k = 0; k < nd; ++k) {
+    U[1 + k] = W[0] * W[1 + k];
+    v2 = v2 + W[1 + k] * W[1 + k];
+  }
+  U[1 + nd] = W[1 + nd] / S(gamma - 1.0) + S(0.5) * W[0] * v2;
+}
+
+// HLLC flux along axis d between the primitive states WL | WR.
+template <class S>
+static void hllc_flux(double gamma, int nd, int d, const S* WL, const S* WR, S* flux) {
+  const int nh = 2 + nd;
+  S UL[5], UR[5], FL[5], FR[5];
+  prim_to_cons(gamma, nd, WL, UL);
+  prim_to_cons(gamma, nd, WR, UR);
+  euler_flux(gamma, nd, d, WL, UL, FL);
+  euler_flux(gamma, nd, d, WR, UR, FR);
+  const S rL = WL[0], rR = WR[0], uL = WL[1 + d], uR = WR[1 + d];
+  const S pL = WL[1 + nd], pR = WR[1 + nd];
+  const S aL = ssqrt(S(gamma) * pL / rL), aR = ssqrt(S(gamma) * pR / rR);
+  const S SL = smin(uL - aL, uR - aR);
+  const S SR = smax(uL + aL, uR + aR);
+  if (!(SL < S(0.0))) {
+    for (int q = 0; q < nh; ++q) flux[q] = FL[q];
+    return;
+  }
+  if (!(SR > S(0.0))) {
+    for (int q = 0; q < nh; ++q) flux[q] = FR[q];
+    return;
+  }
+  const S mL = rL * (SL - uL), mR = rR * (SR - uR);
+  const S Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);   // contact speed S*
+  const bool left = !(Ss < S(0.0));
+  const S* W = left ? WL : WR;
+  const S* U = left ? UL : UR;
+  const S* F = left ? FL : FR;
+  const S SK = left ? SL : SR;
+  const S rK = W[0], uK = W[1 + d], pK = W[1 + nd];
+  const S fac = rK * (SK - uK) / (SK - Ss);
+  S Us[5];
+  Us[0] = fac;
+  for (int k = 0; k < nd; ++k) Us[1 + k] = fac * (k == d ? Ss : W[1 + k]);
+  Us[1 + nd] = fac * (U[1 + nd] / rK + (Ss - uK) * (Ss + pK / (rK * (SK - uK))));
+  for (int q = 0; q < nh; ++q) flux[q] = F[q] + SK * (Us[q] - U[q]);
+}
+
+// L(U) of the gas: srho = -div(rho v), sy rows E_gas and momentum = -div of their
+// fluxes (other rows of sy untouched). U is (rho, y's E_gas and momentum rows).
+static void hydro_rhs(const oracle_params* p, const Grid& g, const double* y, const double* rho,
+                      double* srho, double* sy) {
+  const int nd = g.ndim;
+  const int nh = 2 + nd;   // rho, v_0..v_{nd-1}, p
+  const double gm = p->gamma;
+  for (int64_t c = 0; c < g.N; ++c) srho[c] = 0.0;
+  for (int k = 0; k < nd; ++k)
+    for (int64_t c = 0; c < g.N; ++c) sy[(int64_t)g.vP(k) * g.N + c] = 0.0;
+  for (int64_t c = 0; c < g.N; ++c) sy[(int64_t)g.vEg() * g.N + c] = 0.0;
+  for (int d = 0; d < nd; ++d) {
+    const int64_t nl = g.n[d];
+    int64_t na = (d == 0) ? g.n[1] : g.n[0];
+    int64_t nb = (d == 2) ? g.n[1] : g.n[2];
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t b = 0; b < nb; ++b) {
+      for (int64_t a = 0; a < na; ++a) {
+        auto cell = [&](int64_t t) -> int64_t {
+          if (d == 0) return g.idx(t, a, b);
+          if (d == 1) return g.idx(a, t, b);
+          return g.idx(a, b, t);
+        };
+        // primitive variables along the line with 3 ghosts on each side
+        std::vector<double> ext((size_t)(nl + 6) * nh);
+        for (int64_t t = -3; t < nl + 3; ++t) {
+          bool flip;
+          const int64_t c = cell(ghost_index(t, nl, p->bc[d] == 0 ? 0 : 1, flip));
+          const double r = rho[c];
+          double v2 = 0.0;
+          double* w = &ext[(size_t)(t + 3) * nh];
+          w[0] = r;
+          for (int k = 0; k < nd; ++k) {
+            double v = y[(int64_t)g.vP(k) * g.N + c] / r;
+            v2 += v * v;
+            w[1 + k] = (flip && k == d) ? -v : v;
+          }
+          w[1 + nd] = (gm - 1.0) * (y[(int64_t)g.vEg() * g.N + c] - 0.5 * r * v2);
+        }
+        std::vector<double> eL((size_t)(nl + 2) * nh), eR((size_t)(nl + 2) * nh);
+        for (int64_t t = -1; t <= nl; ++t) {
+          for (int q = 0; q < nh; ++q) {
+            double w5[5];
+            for (int o = -2; o <= 2; ++o) w5[o + 2] = ext[(size_t)(t + o + 3) * nh + q];
+            double aL, aR;
+            ppm_edges(w5, aL, aR);
+            eL[(size_t)(t + 1) * nh + q] = aL;
+            eR[(size_t)(t + 1) * nh + q] = aR;
+          }
+        }
+        std::vector<double> fl((size_t)(nl + 1) * nh);
+        for (int64_t f = 0; f <= nl; ++f)
+          hllc_flux(gm, nd, d, &eR[(size_t)f * nh], &eL[(size_t)(f + 1) * nh], &fl[(size_t)f * nh]);
+        for (int64_t t = 0; t < nl; ++t) {
+          const int64_t c = cell(t);
+          auto div = [&](int q) { return (fl[(size_t)(t + 1) * nh + q] - fl[(size_t)t * nh + q]) / p->dx; };
+          srho[c] -= div(0);
+          for (int k = 0; k < nd; ++k) sy[(int64_t)g.vP(k) * g.N + c] -= div(1 + k);
+          sy[(int64_t)g.vEg() * g.N + c] -= div(1 + nd);
+        }
+      }
+    }
+  }
+}
+
+// One RK2-SSP hydro step of the gas rows of y and of rho; E and F are untouched.
+// Returns ORC_ENONPHYS (first cell in *fail_cell) if rho or the internal energy
+// ends non-positive.
+static int hydro_step(const oracle_params* p, const Grid& g, double* y, double* rho, double dt,
+                      int64_t* fail_cell) {
+  const int nd = g.ndim;
+  const int64_t M = (int64_t)g.nvar * g.N;
+  std::vector<double> y1(y, y + M), r1(rho, rho + g.N), sy((size_t)M), sr((size_t)g.N);
+  std::vector<int> rows;
+  rows.push_back(g.vEg());
+  for (int k = 0; k < nd; ++k) rows.push_back(g.vP(k));
+  hydro_rhs(p, g, y, rho, sr.data(), sy.data());
+  for (int64_t c = 0; c < g.N; ++c) r1[c] = rho[c] + dt * sr[c];
+  for (int r : rows)
+    for (int64_t c = 0; c < g.N; ++c) y1[(int64_t)r * g.N + c] = y[(int64_t)r * g.N + c] + dt * sy[(int64_t)r * g.N + c];
+  hydro_rhs(p, g, y1.data(), r1.data(), sr.data(), sy.data());
+  for (int64_t c = 0; c < g.N; ++c) rho[c] = 0.5 * (rho[c] + r1[c] + dt * sr[c]);
+  for (int r : rows)
+    for (int64_t c = 0; c < g.N; ++c) {
+      const int64_t q = (int64_t)r * g.N + c;
+      y[q] = 0.5 * (y[q] + y1[q] + dt * sy[q]);
+    }
+  int status = ORC_OK;
+  for (int64_t c = 0; c < g.N; ++c) {
+    double m2 = 0.0;
+    for (int k = 0; k < nd; ++k) m2 += y[(int64_t)g.vP(k) * g.N + c] * y[(int64_t)g.vP(k) * g.N + c];
+    const double eint = y[(int64_t)g.vEg() * g.N + c] - 0.5 * m2 / rho[c];
+    if (!(rho[c] > 0.0) || !(eint > 0.0)) {
+      if (*fail_cell < 0 || c < *fail_cell) *fail_cell = c;
+      status = ORC_ENONPHYS;
+      break;
+    }
+  }
+  return status;
+}
+
+// ---------------------------------------------------------------------------
 // C entry points (double and dual). All arrays are host arrays.
 // ---------------------------------------------------------------------------
 extern "C" {
@@ -817,6 +995,49 @@ int oracle_step_dual(const oracle_params* p, double* y, double* ty, const double
     pdars_step(p, g, Y.data(), R.data(), KP.data(), KF.data(), KE.data(), jS ? JS.data() : nullptr,
                dt, yh, s, &status, &fc);
   for (int64_t q = 0; q < M; ++q) { y[q] = Y[q].v; ty[q] = Y[q].d; }
+  if (fail_cell) *fail_cell = fc;
+  return status;
+}
+
+// Hydro: nsteps RK2-SSP steps of dt on (rho, y's E_gas and momentum rows).
+int oracle_hydro_step(const oracle_params* p, double* y, double* rho, double dt, int nsteps,
+                      int64_t* fail_cell) {
+  Grid g(p);
+  int64_t fc = -1;
+  int status = ORC_OK;
+  for (int n = 0; n < nsteps && status == ORC_OK; ++n) status = hydro_step(p, g, y, rho, dt, &fc);
+  if (fail_cell) *fail_cell = fc;
+  return status;
+}
+
+// L(U) of the gas: srho (N) and sy (nvar x N; only the E_gas and momentum rows
+// are written, the radiation rows are set to zero).
+void oracle_hydro_rhs(const oracle_params* p, const double* y, const double* rho, double* srho,
+                      double* sy) {
+  Grid g(p);
+  for (int64_t q = 0; q < (int64_t)g.nvar * g.N; ++q) sy[q] = 0.0;
+  hydro_rhs(p, g, y, rho, srho, sy);
+}
+
+// HLLC flux along axis d between primitive states (rho, v_0..v_{nd-1}, p).
+void oracle_hllc(double gamma, int nd, int d, const double* WL, const double* WR, double* flux) {
+  hllc_flux(gamma, nd, d, WL, WR, flux);
+}
+
+// Operator-split radiation hydrodynamics (Sec. 3.1): per step, one hydro step of
+// dt, then nsub radiation steps of dt / nsub (the radiation is subcycled).
+int oracle_rhd_step(const oracle_params* p, double* y, double* rho, const double* kP,
+                    const double* kF, const double* kE, const double* jS, double dt, int nsub,
+                    int nsteps, int64_t* fail_cell) {
+  Grid g(p);
+  std::vector<double> yh((size_t)g.nvar * g.N), s((size_t)g.nvar * g.N);
+  int status = ORC_OK;
+  int64_t fc = -1;
+  for (int n = 0; n < nsteps && status == ORC_OK; ++n) {
+    status = hydro_step(p, g, y, rho, dt, &fc);
+    for (int m = 0; m < nsub && status == ORC_OK; ++m)
+      pdars_step(p, g, y, rho, kP, kF, kE, jS, dt / nsub, yh, s, &status, &fc);
+  }
   if (fail_cell) *fail_cell = fc;
   return status;
 }

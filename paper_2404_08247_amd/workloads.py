@@ -313,4 +313,67 @@ def marshak(n: int = 60, cfl: float = 10.0, scheme: str = "pdars", t_end: Option
                     np.full(shape, m["kappa"]), None, t_end / nsteps, nsteps)
 
 
+# The advecting radiation pulse (Sec. 5.4 static and Sec. 5.5 dynamic diffusion
+# limit), in cgs.
+PULSE = dict(a_r=7.5657e-15, c=2.99792458e10, k_B=1.380649e-16, mu=3.9e-24, T0=1e7, T1=2e7,
+             width=24.0, rho0=1.2, half_length=512.0, t_end=4.8e-5)
+
+
+@dataclasses.dataclass
+class CoupledWorkload:
+    """A radiation-hydrodynamics run: operator-split steps of dt (one hydro step,
+    then nsub radiation steps of dt / nsub)."""
+    name: str
+    w: Workload          # state, density, opacities and radiation parameters
+    dt: float            # hydro step
+    nsub: int            # radiation steps per hydro step
+    nsteps: int          # hydro steps to t_end
+    shift_cells: int     # v0 t_end / dx (the advected run's displacement)
+
+
+def advecting_pulse(regime: str = "static", advected: bool = True, hydro_cfl: float = 0.3,
+                    rad_cfl: float = 4.0, t_end: Optional[float] = None, **over) -> CoupledWorkload:
+    """1-D periodic radiation pulse on (-512, 512) cm in pressure balance:
+    T = T0 + (T1 - T0) exp(-x^2 / (2 w^2)), rho = rho0 T0/T + (a_r mu / (3 k_B))
+    (T0^4/T - T^3), T_rad = T_gas, mu = 3.9e-24 g, Eddington closure, chat = c,
+    kappa_P = kappa_E = kappa_F. "static": 512 cells, kappa = 100 cm^2/g,
+    v0 = 1e6 cm/s; "dynamic": 1024 cells, kappa = 500, v0 = 3e7. advected: the gas
+    moves at v0 (with the comoving-equilibrium flux F = 4/3 v0 E), else it starts at
+    rest. dt = hydro_cfl dx / max(|v| + c_s) of the initial state, rounded so that an
+    integer number of steps ends at t_end (default 4.8e-5 s); the radiation is
+    subcycled with nsub = ceil(dt c / (rad_cfl dx)) steps per hydro step."""
+    m = PULSE
+    n, kappa, v0 = (512, 100.0, 1e6) if regime == "static" else (1024, 500.0, 3e7)
+    t_end = m["t_end"] if t_end is None else t_end
+    L = 2.0 * m["half_length"]
+    dx = L / n
+    x = -m["half_length"] + (np.arange(n) + 0.5) * dx
+    T = m["T0"] + (m["T1"] - m["T0"]) * np.exp(-x ** 2 / (2.0 * m["width"] ** 2))
+    ar, kB, mu = m["a_r"], m["k_B"], m["mu"]
+    rho = m["rho0"] * m["T0"] / T + ar * mu / (3.0 * kB) * (m["T0"] ** 4 / T - T ** 3)
+    gamma = 5.0 / 3.0
+    p = dict(ndim=1, n=(n, 1, 1), dx=dx, c=m["c"], chat=m["c"], gamma=gamma, a_r=ar,
+             kB_over_mu=kB / mu, bc=(0, 0, 0), closure="eddington", v_order=2, precision="fp64",
+             newton_rtol=1e-13, outer_rtol=1e-13, newton_maxit=50, outer_maxit=10)
+    p.update(over)
+    v = v0 if advected else 0.0
+    cv = kB / mu / (gamma - 1.0)
+    shape = (1, 1, n)
+    E = ar * T ** 4
+    y = np.zeros((4,) + shape)
+    y[0] = E.reshape(shape)
+    y[1] = (4.0 / 3.0 * v * E).reshape(shape)
+    y[2] = (rho * cv * T + 0.5 * rho * v * v).reshape(shape)
+    y[3] = (rho * v).reshape(shape)
+    cs = np.sqrt(gamma * kB * T / mu)
+    dt_max = hydro_cfl * dx / (np.abs(v) + cs).max()
+    nsteps = int(np.ceil(t_end / dt_max))
+    dt = t_end / nsteps
+    nsub = int(np.ceil(dt * m["c"] / (rad_cfl * dx)))
+    name = f"pulse_{regime}_{'advected' if advected else 'rest'}_{n}"
+    w = Workload(name, 1, p["n"], p, y, rho.reshape(shape).copy(), np.full(shape, kappa), None,
+                 dt / nsub, nsub * nsteps)
+    return CoupledWorkload(name, w, dt, nsub, nsteps, int(round(v * t_end / dx)))
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
