@@ -176,6 +176,30 @@ rhd_status rhd_conserved_totals(rhd_handle* h, const double* state, double* out)
 rhd_status rhd_set_energy_opacity(rhd_handle* h, const double* kappa_E);
 rhd_status rhd_set_radiation_source(rhd_handle* h, const double* j);
 
+/* Radiation hydrodynamics by operator splitting (Sec. 3.1): the explicit
+ * hydrodynamics of the gas, then the radiation step subcycled over it.
+ * rhd_hydro_step: nsteps RK2-SSP steps of size dt > 0 of the Euler equations for
+ *   rho, rho v and E_gas (ideal gas, p = (gamma - 1)(E_gas - rho |v|^2 / 2)): PPM
+ *   edge states of (rho, v, p) and HLLC fluxes; periodic axes wrap, the others
+ *   mirror the gas with the normal velocity negated (RHD_BC_INFLOW axes included:
+ *   their inflow state is radiation only). state (device float64 [nvar][nz][ny][nx])
+ *   has its E_gas and momentum rows advanced, E and F untouched; rho (device
+ *   float64 [nz][ny][nx]) is advanced in place and must be the density bound at
+ *   rhd_create, so that the radiation step sees the new values (RHD_EINVAL
+ *   otherwise). The opacities stay per unit mass (chi = rho kappa). CFL is the
+ *   caller's: dt <= C dx / max(|v| + c_s), see rhd_hydro_signal_speed. Returns
+ *   RHD_ENONPHYS with the smallest failing cell if rho or the internal energy
+ *   ends non-positive. Uses the handle's workspace (the RK2 intermediate state).
+ * rhd_rhd_step: nsteps split steps; each is one hydro step of dt followed by nsub
+ *   >= 1 radiation steps (rhd_step) of dt / nsub. Arguments as above.
+ * rhd_hydro_signal_speed: *out (HOST double) = max over cells and axes of
+ *   |v_d| + c_s, c_s = sqrt(gamma p / rho), for choosing dt. */
+rhd_status rhd_hydro_step(rhd_handle* h, double* state, double* rho, double dt, int32_t nsteps);
+rhd_status rhd_rhd_step(rhd_handle* h, double* state, double* rho, double dt, int32_t nsub,
+                        int32_t nsteps);
+rhd_status rhd_hydro_signal_speed(rhd_handle* h, const double* state, const double* rho,
+                                  double* out);
+
 /* Error details of the last call on h: *cell = smallest failing cell index (or
  * -1), msg receives a NUL-terminated description (truncated to len). Returns the
  * status of the last call. */

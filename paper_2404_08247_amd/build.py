@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librhd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["rhd_forward.hip", "rhd_adjoint.hip", "rhd_api.cpp"]
+SOURCES = ["rhd_forward.hip", "rhd_adjoint.hip", "rhd_hydro.hip", "rhd_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -3,6 +3,7 @@
 // device error word. No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -141,6 +142,9 @@ rhd::DevParams make_dev(const rhd_params* p, bool alias) {
   d.inv_c_chat = 1.0 / (p->c * p->chat);
   d.inv_c2 = 1.0 / (p->c * p->c);
   d.a_r = p->a_r;
+  d.gamma = p->gamma;
+  d.gm1 = p->gamma - 1.0;
+  d.inv_gm1 = 1.0 / d.gm1;
   d.cv_mass = p->kB_over_mu / (p->gamma - 1.0);
   d.inv_cv_mass = 1.0 / d.cv_mass;
   d.newton_rtol = p->newton_rtol;
@@ -344,6 +348,73 @@ rhd_status rhd_conserved_totals(rhd_handle* h, const double* state, double* out)
   for (int m = 0; m < no; ++m) out[m] = 0.0;
   for (int b = 0; b < h->partial_blocks; ++b)
     for (int m = 0; m < no; ++m) out[m] += part[(size_t)b * no + m];
+  return set_err(h, RHD_OK, -1, "");
+}
+
+// Hydro arguments: state and rho valid and aligned, rho the bound density.
+static rhd_status hydro_args(rhd_handle* h, const double* state, const double* rho, double dt) {
+  if (!state || !rho || misaligned(state) || misaligned(rho) || !std::isfinite(dt) || !(dt > 0.0))
+    return set_err(h, RHD_EINVAL, -1, "invalid state, rho or dt");
+  if (rho != h->rho)
+    return set_err(h, RHD_EINVAL, -1, "rho must be the density bound at rhd_create");
+  return RHD_OK;
+}
+
+rhd_status rhd_hydro_step(rhd_handle* h, double* state, double* rho, double dt, int32_t nsteps) {
+  if (!h) return RHD_EINVAL;
+  if (nsteps < 0) return set_err(h, RHD_EINVAL, -1, "nsteps must be >= 0");
+  rhd_status st = hydro_args(h, state, rho, dt);
+  if (st != RHD_OK) return st;
+  hipError_t e = rhd::launch_reset_err(h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset");
+  for (int n = 0; n < nsteps; ++n) {
+    e = rhd::launch_hydro_step(h->dp, state, rho, h->yhalf, dt, h->err, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hydro launch");
+  }
+  return finish(h);
+}
+
+rhd_status rhd_rhd_step(rhd_handle* h, double* state, double* rho, double dt, int32_t nsub,
+                        int32_t nsteps) {
+  if (!h) return RHD_EINVAL;
+  if (nsteps < 0 || nsub < 1) return set_err(h, RHD_EINVAL, -1, "need nsteps >= 0 and nsub >= 1");
+  rhd_status st = hydro_args(h, state, rho, dt);
+  if (st != RHD_OK) return st;
+  const bool mixed = (h->p.precision == RHD_MIXED);
+  const double dtr = dt / nsub;
+  hipError_t e = rhd::launch_reset_err(h->err, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reset");
+  for (int n = 0; n < nsteps; ++n) {
+    e = rhd::launch_hydro_step(h->dp, state, rho, h->yhalf, dt, h->err, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hydro launch");
+    for (int m = 0; m < nsub; ++m) {
+      e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, mixed, state, state, h->yhalf, h->rho, h->kP,
+                            h->kF, dtr, h->err, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "stage 1 launch");
+      e = rhd::launch_stage(h->dp, rhd::MODE_STAGE2, mixed, h->yhalf, state, state, h->rho, h->kP,
+                            h->kF, dtr, h->err, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "stage 2 launch");
+    }
+  }
+  return finish(h);
+}
+
+rhd_status rhd_hydro_signal_speed(rhd_handle* h, const double* state, const double* rho,
+                                  double* out) {
+  if (!h) return RHD_EINVAL;
+  if (!out || !state || !rho || misaligned(state) || misaligned(rho))
+    return set_err(h, RHD_EINVAL, -1, "invalid state, rho or out");
+  hipError_t e = rhd::launch_hydro_speed(h->dp, state, rho, h->partial, h->partial_blocks, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "signal speed launch");
+  std::vector<double> part((size_t)h->partial_blocks);
+  e = hipMemcpyAsync(part.data(), h->partial, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                     h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpyAsync(signal speed)");
+  e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  double m = 0.0;
+  for (double x : part) m = std::max(m, x);
+  *out = m;
   return set_err(h, RHD_OK, -1, "");
 }
 

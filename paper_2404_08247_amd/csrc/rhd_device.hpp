@@ -89,6 +89,30 @@ __device__ __forceinline__ void ppm_monotone(T& l, T& r) {
   r = nr;
 }
 
+// Ghost rule along one axis: returns the source cell of (possibly outside)
+// coordinate g and whether the normal vector component (radiation flux or gas
+// velocity) flips sign (bc 0 periodic, any other kind mirrors). Positions
+// further than 3 cells outside the grid are clamped; no real cell's stencil
+// reads them.
+__device__ __forceinline__ int ghost(int g, int n, int bc, bool& flip) {
+  flip = false;
+  if (g >= 0 && g < n) return g;
+  if (bc == 0) {
+    if (g < 0 && g + n >= 0) return g + n;   // one period away
+    if (g >= n && g - n < n) return g - n;
+    int m = g % n;
+    return m < 0 ? m + n : m;
+  }
+  flip = true;
+  int m = (g < 0) ? -1 - g : 2 * n - 1 - g;
+  return m < 0 ? 0 : (m >= n ? n - 1 : m);
+}
+
+__device__ __forceinline__ void report(unsigned long long* err, long long cell, unsigned bits) {
+  atomicMin(err, (unsigned long long)cell);
+  atomicOr(reinterpret_cast<unsigned int*>(err + 1), bits);
+}
+
 // edge states of the middle cell of a[0..4] (double values in, double out)
 template <typename T>
 __device__ __forceinline__ void ppm_edges5(double a0, double a1, double a2, double a3, double a4,

@@ -51,29 +51,6 @@ template <> struct TileShape<1> { static constexpr int TX = 256, TY = 1; };
 template <> struct TileShape<2> { static constexpr int TX = RHD_TX, TY = 256 / RHD_TX; };
 template <> struct TileShape<3> { static constexpr int TX = RHD_TX, TY = 256 / RHD_TX; };
 
-// Ghost rule along one axis: returns the source cell of (possibly outside)
-// coordinate g and whether the normal flux component flips sign. Positions
-// further than HALO outside the grid are clamped; no real cell's stencil
-// reads them.
-__device__ __forceinline__ int ghost(int g, int n, int bc, bool& flip) {
-  flip = false;
-  if (g >= 0 && g < n) return g;
-  if (bc == 0) {
-    if (g < 0 && g + n >= 0) return g + n;   // one period away
-    if (g >= n && g - n < n) return g - n;
-    int m = g % n;
-    return m < 0 ? m + n : m;
-  }
-  flip = true;
-  int m = (g < 0) ? -1 - g : 2 * n - 1 - g;
-  return m < 0 ? 0 : (m >= n ? n - 1 : m);
-}
-
-__device__ __forceinline__ void report(unsigned long long* err, long long cell, unsigned bits) {
-  atomicMin(err, (unsigned long long)cell);
-  atomicOr(reinterpret_cast<unsigned int*>(err + 1), bits);
-}
-
 // Value of radiation variable r (E, F_1..F_ND) in a ghost cell below an inflow
 // axis: the fixed inflow state, with its flux along the axis.
 __device__ __forceinline__ double inflow_value(const DevParams& P, int r, int axis) {

@@ -22,6 +22,7 @@ struct DevParams {
   double c, chat;
   double c_over_chat, chat_over_c, c_chat, inv_c_chat, inv_c2;
   double a_r;
+  double gamma, gm1, inv_gm1;   // adiabatic index, gamma - 1, 1 / (gamma - 1)
   double cv_mass;     // kB_over_mu / (gamma - 1)
   double inv_cv_mass; // 1 / cv_mass
   double newton_rtol, outer_rtol;
@@ -50,6 +51,13 @@ hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* 
 hipError_t launch_source(const DevParams& P, double* y, const double* rho, const double* kP,
                          const double* kF, double tau, unsigned long long* err, hipStream_t s);
 hipError_t launch_reset_err(unsigned long long* err, hipStream_t s);
+// rhd_hydro.hip: one RK2-SSP hydro step of (rho, E_gas, rho v) in place; ws holds
+// (2 + ndim) N doubles (the intermediate state)
+hipError_t launch_hydro_step(const DevParams& P, double* y, double* rho, double* ws, double dt,
+                             unsigned long long* err, hipStream_t s);
+// per-block maxima of max_d |v_d| + c_s into partial[0..nblocks)
+hipError_t launch_hydro_speed(const DevParams& P, const double* y, const double* rho,
+                              double* partial, int nblocks, hipStream_t s);
 hipError_t launch_totals(const DevParams& P, const double* y, double* partial, int nblocks,
                          hipStream_t s);
 

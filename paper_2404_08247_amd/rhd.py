@@ -21,7 +21,8 @@ _STATUS = {0: "RHD_OK", -1: "RHD_EINVAL", -2: "RHD_ENEWTON", -3: "RHD_ENONPHYS",
            -5: "RHD_EWORKSPACE"}
 EXPORTED = ["rhd_workspace_bytes", "rhd_create", "rhd_step", "rhd_step_adjoint", "rhd_transport",
             "rhd_source", "rhd_stage1", "rhd_step_timed", "rhd_conserved_totals", "rhd_last_error",
-            "rhd_destroy", "rhd_set_energy_opacity", "rhd_set_radiation_source"]
+            "rhd_destroy", "rhd_set_energy_opacity", "rhd_set_radiation_source",
+            "rhd_hydro_step", "rhd_rhd_step", "rhd_hydro_signal_speed"]
 
 
 class RHDParams(ctypes.Structure):
@@ -93,6 +94,12 @@ def _load():
     L.rhd_set_energy_opacity.restype = ctypes.c_int
     L.rhd_set_radiation_source.argtypes = [vp, vp]
     L.rhd_set_radiation_source.restype = ctypes.c_int
+    L.rhd_hydro_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32]
+    L.rhd_hydro_step.restype = ctypes.c_int
+    L.rhd_rhd_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32]
+    L.rhd_rhd_step.restype = ctypes.c_int
+    L.rhd_hydro_signal_speed.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+    L.rhd_hydro_signal_speed.restype = ctypes.c_int
     return L
 
 
@@ -222,6 +229,26 @@ class Solver:
         """Radiation injection rate per unit volume (None: no source); kept referenced."""
         self.j_source = j
         return self._check(lib.rhd_set_radiation_source(self._h, _ptr(j)))
+
+    def hydro_step(self, y: torch.Tensor, dt: float, nsteps: int = 1,
+                   raise_on_error: bool = True) -> int:
+        """RK2-SSP hydro steps of the gas rows of y and of the bound density
+        (self.rho, advanced in place)."""
+        return self._check(lib.rhd_hydro_step(self._h, self._state(y), _ptr(self.rho), float(dt),
+                                              int(nsteps)), raise_on_error)
+
+    def rhd_step(self, y: torch.Tensor, dt: float, nsub: int, nsteps: int,
+                 raise_on_error: bool = True) -> int:
+        """Operator-split steps: one hydro step of dt, then nsub radiation steps
+        of dt / nsub, nsteps times (self.rho advanced in place)."""
+        return self._check(lib.rhd_rhd_step(self._h, self._state(y), _ptr(self.rho), float(dt),
+                                            int(nsub), int(nsteps)), raise_on_error)
+
+    def hydro_signal_speed(self, y: torch.Tensor) -> float:
+        out = ctypes.c_double(0.0)
+        self._check(lib.rhd_hydro_signal_speed(self._h, self._state(y), _ptr(self.rho),
+                                               ctypes.byref(out)))
+        return float(out.value)
 
     def conserved_totals(self, y: torch.Tensor):
         out = (ctypes.c_double * (1 + self.ndim))()

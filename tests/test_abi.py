@@ -114,3 +114,27 @@ def test_adjoint_rejects_what_it_does_not_differentiate():
                                 ctypes.c_void_p(1 << 23), ctypes.c_void_p(1 << 24), None)
         assert st == -1, bad
         L.rhd_destroy(h)
+
+
+def test_hydro_entry_points_validate_before_launching():
+    """rhd_hydro_step / rhd_rhd_step reject a density other than the bound one,
+    dt <= 0, nsteps < 0 and nsub < 1 with RHD_EINVAL (no launch)."""
+    from paper_2404_08247_amd import rhd
+    L = rhd.lib
+    p = W.config2(n=(16, 12, 10)).params
+    rp = rhd.make_params(p)
+    nb = L.rhd_workspace_bytes(ctypes.byref(rp), 0)
+    rho = ctypes.c_void_p(1 << 20)
+    other = ctypes.c_void_p(1 << 21)
+    y = ctypes.c_void_p(1 << 22)
+    h = ctypes.c_void_p()
+    assert L.rhd_create(ctypes.byref(rp), rho, other, None, ctypes.c_void_p(1 << 23), nb, 0, None,
+                        ctypes.byref(h)) == 0
+    assert L.rhd_hydro_step(h, y, other, ctypes.c_double(1e-3), 1) == -1
+    assert L.rhd_hydro_step(h, y, rho, ctypes.c_double(0.0), 1) == -1
+    assert L.rhd_hydro_step(h, y, rho, ctypes.c_double(1e-3), -1) == -1
+    assert L.rhd_hydro_step(h, None, rho, ctypes.c_double(1e-3), 1) == -1
+    assert L.rhd_rhd_step(h, y, rho, ctypes.c_double(1e-3), 0, 1) == -1
+    assert L.rhd_rhd_step(h, y, other, ctypes.c_double(1e-3), 2, 1) == -1
+    assert L.rhd_hydro_signal_speed(h, y, rho, None) == -1
+    L.rhd_destroy(h)
