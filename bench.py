@@ -151,6 +151,46 @@ def bench_options(torch, rhd, W, dev, to, nsteps=50):
     return out
 
 
+def bench_hydro(torch, rhd, W, dev, to, nsteps=20):
+    """Operator-split radiation hydrodynamics on the 3-D 128^3 workload with a
+    moving gas (rough density, velocities up to 0.5 c_s): hydro steps alone
+    (per-stage kernel time from the trace is in profiles/), and split steps with
+    4 radiation subcycles per hydro step."""
+    w = W.config2(precision="fp64")
+    rng = np.random.default_rng(91)
+    p = w.params
+    cv = p["kB_over_mu"] / (p["gamma"] - 1.0)
+    T = w.y0[4] / (w.rho * cv)
+    rho = w.rho * (1.0 + 0.3 * rng.uniform(-1, 1, w.rho.shape))
+    cs = np.sqrt(p["gamma"] * p["kB_over_mu"] * T)
+    y = w.y0.copy()
+    v = [0.5 * cs * rng.uniform(-1, 1, rho.shape) for _ in range(3)]
+    for k in range(3):
+        y[5 + k] = rho * v[k]
+    y[4] = rho * cv * T + 0.5 * rho * sum(vk ** 2 for vk in v)
+    rd = to(rho)
+    S = rhd.Solver(p, rd, to(w.kappa_P), None, 0, dev)
+    yd = to(y)
+    smax = S.hydro_signal_speed(yd)
+    dt_h = 0.3 * p["dx"] / smax
+    nsub = 4
+    S.hydro_step(yd, dt_h, 2)
+    t_h = _timed(torch, lambda: S.hydro_step(yd, dt_h, nsteps))
+    rd.copy_(to(rho))
+    yd.copy_(to(y))
+    S.rhd_step(yd, dt_h, nsub, 1)
+    t_s = _timed(torch, lambda: S.rhd_step(yd, dt_h, nsub, nsteps))
+    cells = w.ncells
+    print(f"[bench] hydro: {t_h / nsteps * 1e3:.3f} ms/step; split (1 hydro + {nsub} radiation): "
+          f"{t_s / nsteps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    return {"workload": "3-D 128^3 mixed-regime grid with moving gas (|v| <= 0.5 c_s, density "
+                        "+-30 %), FP64, hydro CFL 0.3",
+            "hydro": {"value": cells * nsteps / t_h, "unit": "cell-updates/s",
+                      "ms_per_step": t_h / nsteps * 1e3},
+            "split": {"value": cells * nsteps / t_s, "unit": "cell-updates/s (hydro steps)",
+                      "ms_per_step": t_s / nsteps * 1e3, "radiation_subcycles": nsub}}
+
+
 def bench_adjoint(torch, rhd, W, dev, to):
     """2-D 512^2 adjoint workload (200 steps, checkpoints every 20): forward with
     checkpoint copies, then the full backward (recompute + reverse of every
@@ -198,7 +238,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60,
                     help="oracle steps in the CPU-baseline sample (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the mixed-precision and adjoint line items")
+                    help="skip the extra line items (same as --extras none)")
+    ap.add_argument("--extras", default="mixed,adjoint,options,hydro",
+                    help="comma list of extra line items: mixed, adjoint, options, hydro, or none")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-mebibyte buffer once (a plain copy "
                          "kernel of known size, to scale the HBM byte counters)")
@@ -254,10 +296,15 @@ def main():
           f"{wall / args.steps * 1e6:.1f} us", file=sys.stderr, flush=True)
 
     extras = {}
-    if not args.no_extras:
+    want = set() if args.no_extras else set(args.extras.split(","))
+    if "mixed" in want:
         extras["mixed_vs_fp64"] = bench_mixed(torch, rhd, W, dev, to)
+    if "adjoint" in want:
         extras["adjoint"] = bench_adjoint(torch, rhd, W, dev, to)
+    if "options" in want:
         extras["options"] = bench_options(torch, rhd, W, dev, to)
+    if "hydro" in want:
+        extras["hydro_coupling"] = bench_hydro(torch, rhd, W, dev, to)
 
     cpu = None
     if args.cpu_steps > 0:
