@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--cpu-steps", type=int, default=60,
                     help="oracle steps in the CPU-baseline sample (0 = skip)")
+    ap.add_argument("--cpu-steps-1t", type=int, default=3,
+                    help="oracle steps of the one-thread CPU sample (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the extra line items (same as --extras none)")
     ap.add_argument("--extras", default="mixed,adjoint,options,hydro",
@@ -317,6 +319,17 @@ def main():
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"first {args.cpu_steps} of the 200 steps of the same 128^3 FP64 "
                          f"workload (OpenMP over cells), {tcpu:.1f} s"}
+        if args.cpu_steps_1t > 0:
+            nt = oracle.num_threads()
+            oracle.set_threads(1)
+            tc = time.perf_counter()
+            oracle.step(wc.params, wc.y0, wc.rho, wc.kappa_P, None, wc.dt, args.cpu_steps_1t)
+            t1c = time.perf_counter() - tc
+            oracle.set_threads(nt)
+            cpu["one_thread"] = {"value": wc.ncells * args.cpu_steps_1t / t1c,
+                                 "unit": "cell-updates/s", "cores": 1,
+                                 "sample": f"first {args.cpu_steps_1t} steps, one thread, "
+                                           f"{t1c:.1f} s"}
 
     line = {
         "metric": "IMEX RHD cell-updates/s, FP64 vs mixed; adjoint/forward time ratio",

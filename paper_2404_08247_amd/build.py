@@ -23,6 +23,12 @@ FLAGS = [
 ]
 
 
+# Per-file device-compiler options: the stage kernels schedule for ILP (measured
+# 1.3 % faster on the 128^3 FP64 step than the default occupancy-driven scheduler,
+# with bitwise-identical results).
+FILE_FLAGS = {"rhd_forward.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]}
+
+
 def build(verbose=False, extra=()):
     objs = []
     for src in SOURCES:
@@ -31,7 +37,7 @@ def build(verbose=False, extra=()):
             continue
         obj = os.path.join(CSRC, src + ".o")
         # hipcc compiles the host-only .cpp as HIP too: same target and flags
-        cmd = [HIPCC, *FLAGS, *extra, "-c", path, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(src, []), *extra, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
