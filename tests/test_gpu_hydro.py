@@ -206,3 +206,54 @@ def test_advecting_pulse_on_gpu(torch_dev, regime, hydro_cfl, bound, eq_bound):
         assert abs(r.sum() - w.rho.sum()) < 1e-13 * w.rho.sum()
         e0 = (w.y0[2] + k * w.y0[0]).sum()
         assert abs((y[2] + k * y[0]).sum() - e0) < 1e-12 * e0
+
+
+def _tiny_workload(n, bc, seed):
+    """config5's parameters on a tiny grid with an i.i.d. random state (the
+    workload generators' smooth random fields need more than a few cells)."""
+    base = W.config5(n=(8, 8, 8), precision="fp64")
+    p = W.base_params(3, n, base.params["chat"], bc, precision="fp64")
+    rng = np.random.default_rng(seed)
+    shape = (n[2], n[1], n[0])
+    T = 1.0 + 0.2 * rng.uniform(-1, 1, shape)
+    E = p["a_r"] * (T * (1.0 + 0.2 * rng.uniform(-1, 1, shape))) ** 4
+    cv = p["kB_over_mu"] / (p["gamma"] - 1.0)
+    y = np.zeros((8,) + shape)
+    y[0] = E
+    for d in range(3):
+        y[1 + d] = 0.3 * p["c"] * E * rng.uniform(-1, 1, shape) / np.sqrt(3.0)
+    rho = np.ones(shape)
+    y[4] = rho * cv * T
+    p["inflow_E"] = float(E.mean())   # used only by inflow axes
+    kappa = 10.0 ** rng.uniform(-2, 2, shape) / p["dx"]
+    return W.Workload("tiny", 3, p["n"], p, y, rho, kappa, None, 0.3 * p["dx"] / p["chat"], 2)
+
+
+TINY = [((1, 1, 1), (0, 0, 0)), ((2, 3, 5), (0, 0, 0)), ((3, 3, 3), (1, 1, 1)),
+        ((4, 3, 7), (2, 1, 0)), ((5, 1, 1), (1, 0, 0))]
+
+
+@pytest.mark.parametrize("n,bc", TINY)
+def test_tiny_grids_radiation_and_split_steps_match_oracle(torch_dev, orc, n, bc):
+    """Degenerate sizes (one cell, extents below the 3-cell halo, single-cell
+    axes): the periodic wrap and the mirror reach across the whole axis."""
+    w = _tiny_workload(n, bc, 41)
+    w, smax = _moving_gas(w, 41, vmax_over_cs=0.3)
+    _say("tiny", n, bc)
+    ref, st, _ = orc.step(w.params, w.y0, w.rho, w.kappa_P, None, w.dt, 2)
+    assert st == 0
+    rho = _to(torch_dev, w.rho)
+    S = _solver(torch_dev, w, rho)
+    yd = _to(torch_dev, w.y0)
+    S.step(yd, w.dt, 2)
+    got = yd.cpu().numpy()
+    err = max(_rel(got[v], ref[v]) for v in range(w.nvar))
+    assert err < 1e-10, err
+    dt = min(0.3 * w.params["dx"] / smax, w.dt)
+    ref_y, ref_r, st, _ = orc.rhd_step(w.params, w.y0, w.rho, w.kappa_P, None, dt, 2, 2)
+    assert st == 0
+    yd = _to(torch_dev, w.y0)
+    S.rhd_step(yd, dt, 2, 2)
+    got = yd.cpu().numpy()
+    err = max([_rel(got[v], ref_y[v]) for v in range(w.nvar)] + [_rel(rho.cpu().numpy(), ref_r)])
+    assert err < 1e-10, err
