@@ -162,8 +162,6 @@ template <int N> __device__ __forceinline__ DT<N> sabs(const DT<N>& a) { return 
 template <> __device__ __forceinline__ DT<3> mk0<DT<3>>(double x) { return dtc<3>(x); }
 template <> __device__ __forceinline__ DT<4> mk0<DT<4>>(double x) { return dtc<4>(x); }
 template <> __device__ __forceinline__ DT<2> mk0<DT<2>>(double x) { return dtc<2>(x); }
-using D5 = DT<5>;
-__device__ __forceinline__ D5 d5zero() { return dtc<5>(0.0); }
 
 // PPM (same method as the forward) on a piecewise-linear scalar type: the
 // tangents of the active branch are carried along.
@@ -205,6 +203,69 @@ __device__ __forceinline__ void ppm_edges_s(const S& a0, const S& a1, const S& a
   }
   l = a2 + lo;
   r = a2 + ro;
+}
+
+// Partial derivatives (kl, kr) of the slope slope_s(dl, dr) in its active branch:
+// 0 across an extremum, 1/2 each for the centred slope, 2 for a limiting side.
+__device__ __forceinline__ void slope_partials(double dl, double dr, double& kl, double& kr) {
+  kl = 0.0;
+  kr = 0.0;
+  if (!(dl * dr > 0.0)) return;
+  const double adc = fabs(0.5 * (dl + dr)), adl = 2.0 * fabs(dl), adr = 2.0 * fabs(dr);
+  if (adc <= adl && adc <= adr) {
+    kl = 0.5;
+    kr = 0.5;
+  } else if (adl <= adr) {
+    kl = 2.0;
+  } else {
+    kr = 2.0;
+  }
+}
+
+// Reverse-mode derivative of ppm_edges_s: ga[o] = gl dl/da_o + gr dr/da_o for the
+// edges (l, r) of the middle cell of a0..a4, in the forward's branches (the map is
+// linear within a branch: this is one reverse sweep instead of five tangents).
+__device__ __forceinline__ void ppm_edges_vjp(double a0, double a1, double a2, double a3,
+                                              double a4, double gl, double gr, double* ga) {
+  const double d01 = a1 - a0, d12 = a2 - a1, d23 = a3 - a2, d34 = a4 - a3;
+  const double s1 = slope_s(d01, d12, 0.0), s2 = slope_s(d12, d23, 0.0);
+  const double s3 = slope_s(d23, d34, 0.0);
+  const double lo = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
+  const double ro = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
+  double glo, gro;   // adjoints of the raw offsets through the monotonicity constraint
+  if (ro * lo >= 0.0) {
+    glo = 0.0;
+    gro = 0.0;
+  } else {
+    const double del = ro - lo;
+    const double a6 = -3.0 * (lo + ro);
+    if (del * a6 > del * del) {            // l = a2 - 2 ro, r = a2 + ro
+      glo = 0.0;
+      gro = gr - 2.0 * gl;
+    } else if (del * a6 < -(del * del)) {  // r = a2 - 2 lo, l = a2 + lo
+      glo = gl - 2.0 * gr;
+      gro = 0.0;
+    } else {
+      glo = gl;
+      gro = gr;
+    }
+  }
+  const double gs1 = (1.0 / 6.0) * glo;
+  const double gs2 = (1.0 / 6.0) * (gro - glo);
+  const double gs3 = -(1.0 / 6.0) * gro;
+  double k1l, k1r, k2l, k2r, k3l, k3r;
+  slope_partials(d01, d12, k1l, k1r);
+  slope_partials(d12, d23, k2l, k2r);
+  slope_partials(d23, d34, k3l, k3r);
+  const double g01 = k1l * gs1;
+  const double g12 = -0.5 * glo + k1r * gs1 + k2l * gs2;
+  const double g23 = 0.5 * gro + k2r * gs2 + k3l * gs3;
+  const double g34 = k3r * gs3;
+  ga[0] = -g01;
+  ga[1] = g01 - g12;
+  ga[2] = g12 - g23 + gl + gr;
+  ga[3] = g23 - g34;
+  ga[4] = g34;
 }
 
 // Row DIR of the closure tensor, D_DIR,k(U) for k < ND, U = (E, F_1..F_ND), on a
@@ -627,17 +688,11 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
       if (p0 + p < np) {
         const double mum = s_fm[r][p][c + 1];      // its right face, w.r.t. aR
         const double mup = s_fm[NR + r][p][c];     // its left face, w.r.t. aL
-        D5 a[5];
+        const double* a = &s_y[r][p][c + 1];
+        double ga[5];
+        ppm_edges_vjp(a[0], a[1], a[2], a[3], a[4], mup, mum, ga);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) {
-          a[o] = d5zero();
-          a[o].v = s_y[r][p][c + 1 + o];
-          a[o].d[o] = 1.0;
-        }
-        D5 l, rr;
-        ppm_edges_s<D5>(a[0], a[1], a[2], a[3], a[4], l, rr, d5zero());
-#pragma unroll
-        for (int o = 0; o < 5; ++o) s_c[o][p][c] = rr.d[o] * mum + l.d[o] * mup;
+        for (int o = 0; o < 5; ++o) s_c[o][p][c] = ga[o];
       }
     }
     __syncthreads();
