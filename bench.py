@@ -191,12 +191,14 @@ def bench_hydro(torch, rhd, W, dev, to, nsteps=20):
                       "ms_per_step": t_s / nsteps * 1e3, "radiation_subcycles": nsub}}
 
 
-def bench_adjoint(torch, rhd, W, dev, to):
-    """2-D 512^2 adjoint workload (200 steps, checkpoints every 20): forward with
+def bench_adjoint(torch, rhd, W, dev, to, config=4):
+    """Adjoint workloads: config 4, 2-D 512^2 FP64 (200 steps, checkpoints every 20,
+    J = sum of E over the central 64^2 patch), or config 5, 3-D 320^3 mixed precision
+    (100 steps, checkpoints every 10, J over the central 64^3 block). Forward with
     checkpoint copies, then the full backward (recompute + reverse of every
-    segment), J = sum of E over the central 64^2 patch."""
+    segment), gradients with respect to kappa and the initial temperature."""
     from paper_2404_08247_amd import autograd as AG
-    w = W.config4()
+    w = W.config4() if config == 4 else W.config5()
     p = w.params
     nd = w.ndim
     cv = p["kB_over_mu"] / (p["gamma"] - 1)
@@ -204,6 +206,7 @@ def bench_adjoint(torch, rhd, W, dev, to):
     T0 = to((w.y0[1 + nd] - ke) / (w.rho * cv))
     rho, kap = to(w.rho), to(w.kappa_P)
     mom, mask = to(w.y0[2 + nd:]), to(w.objective_mask.astype(np.float64))
+    w.y0 = None
     S = rhd.Solver(p, rho, kap, None, w.ckpt_every, dev)
     kap.requires_grad_(True)
     T = T0.clone().requires_grad_(True)
@@ -220,13 +223,18 @@ def bench_adjoint(torch, rhd, W, dev, to):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     fwd, bwd = t1 - t0, t2 - t1
-    print(f"[bench] c4 adjoint: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms",
+    print(f"[bench] c{config} adjoint: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms",
           file=sys.stderr, flush=True)
-    return {"workload": "2-D 512^2, periodic, chat = c, 200 steps, checkpoints every 20",
-            "forward_s": fwd, "backward_s": bwd, "adjoint_forward_ratio": bwd / fwd,
-            "forward_cell_updates_per_s": w.ncells * w.nsteps / fwd,
-            "J": float(J.item()), "grad_norm_kappa": float(gk.norm().item()),
-            "grad_norm_T0": float(gT.norm().item())}
+    desc = ("2-D 512^2, FP64, periodic, chat = c, 200 steps, checkpoints every 20" if config == 4 else
+            "3-D 320^3, mixed precision (FP64 adjoint), periodic, chat = c/100, 100 steps, "
+            "checkpoints every 10")
+    out = {"workload": desc, "forward_s": fwd, "backward_s": bwd, "adjoint_forward_ratio": bwd / fwd,
+           "forward_cell_updates_per_s": w.ncells * w.nsteps / fwd,
+           "J": float(J.item()), "grad_norm_kappa": float(gk.norm().item()),
+           "grad_norm_T0": float(gT.norm().item())}
+    del S, yN, y0, gT, gk, J
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -241,8 +249,9 @@ def main():
                     help="oracle steps of the one-thread CPU sample (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the extra line items (same as --extras none)")
-    ap.add_argument("--extras", default="mixed,adjoint,options,hydro",
-                    help="comma list of extra line items: mixed, adjoint, options, hydro, or none")
+    ap.add_argument("--extras", default="mixed,adjoint,adjoint5,options,hydro",
+                    help="comma list of extra line items: mixed, adjoint (config 4), adjoint5 "
+                         "(config 5), options, hydro, or none")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-mebibyte buffer once (a plain copy "
                          "kernel of known size, to scale the HBM byte counters)")
@@ -302,7 +311,9 @@ def main():
     if "mixed" in want:
         extras["mixed_vs_fp64"] = bench_mixed(torch, rhd, W, dev, to)
     if "adjoint" in want:
-        extras["adjoint"] = bench_adjoint(torch, rhd, W, dev, to)
+        extras["adjoint"] = bench_adjoint(torch, rhd, W, dev, to, 4)
+    if "adjoint5" in want:
+        extras["adjoint_c5"] = bench_adjoint(torch, rhd, W, dev, to, 5)
     if "options" in want:
         extras["options"] = bench_options(torch, rhd, W, dev, to)
     if "hydro" in want:

@@ -53,19 +53,26 @@ __device__ __forceinline__ Dd operator+(Dd a, double b) { return mk(a.v + b, a.d
 __device__ __forceinline__ Dd operator+(double a, Dd b) { return mk(a + b.v, b.d); }
 __device__ __forceinline__ Dd operator-(double a, Dd b) { return mk(a - b.v, -b.d); }
 __device__ __forceinline__ Dd operator-(Dd a, double b) { return mk(a.v - b, a.d); }
+// Quotients and square roots of the derivative types use the refined hardware
+// reciprocal and square root (rhd_device.hpp): they feed derivatives only.
 __device__ __forceinline__ Dd operator/(Dd a, Dd b) {
-  const double q = a.v / b.v;
-  return mk(q, (a.d - q * b.d) / b.v);
+  const double ib = rcp(b.v);
+  const double q = a.v * ib;
+  return mk(q, (a.d - q * b.d) * ib);
 }
 __device__ __forceinline__ Dd operator/(double a, Dd b) {
-  const double q = a / b.v;
-  return mk(q, -q * b.d / b.v);
+  const double ib = rcp(b.v);
+  const double q = a * ib;
+  return mk(q, -q * b.d * ib);
 }
 __device__ __forceinline__ Dd dsqrt(Dd a) {
-  const double s = sqrt(a.v);
-  return mk(s, s > 0.0 ? a.d / (2.0 * s) : 0.0);
+  const double s = sqrt_nonneg(a.v);
+  return mk(s, s > 0.0 ? a.d * (0.5 * rcp(s)) : 0.0);
 }
-__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ double dsqrt(double a) { return sqrt_nonneg(a); }
+// 1/x on double or a derivative type
+__device__ __forceinline__ double dinv(double x) { return rcp(x); }
+__device__ __forceinline__ Dd dinv(Dd x) { return 1.0 / x; }
 __device__ __forceinline__ double vof(double a) { return a; }
 __device__ __forceinline__ double vof(Dd a) { return a.v; }
 template <typename S> __device__ __forceinline__ S smax(S a, S b) { return vof(a) < vof(b) ? b : a; }
@@ -140,17 +147,28 @@ template <int N> __device__ __forceinline__ DT<N> operator-(double a, const DT<N
   return (-b) + a;
 }
 template <int N> __device__ __forceinline__ DT<N> operator/(double a, const DT<N>& b) {
-  const double q = a / b.v;
-  const double s = -q / b.v;
+  const double ib = rcp(b.v);
+  const double q = a * ib;
+  const double s = -q * ib;
   DT<N> r;
   r.v = q;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = s * b.d[i];
   return r;
 }
+template <int N> __device__ __forceinline__ DT<N> operator/(const DT<N>& a, const DT<N>& b) {
+  const double ib = rcp(b.v);
+  const double q = a.v * ib;
+  DT<N> r;
+  r.v = q;
+#pragma unroll
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - q * b.d[i]) * ib;
+  return r;
+}
+template <int N> __device__ __forceinline__ DT<N> dinv(const DT<N>& x) { return 1.0 / x; }
 template <int N> __device__ __forceinline__ DT<N> dsqrt(const DT<N>& a) {
-  const double sq = sqrt(a.v);
-  const double f = sq > 0.0 ? 0.5 / sq : 0.0;
+  const double sq = sqrt_nonneg(a.v);
+  const double f = sq > 0.0 ? 0.5 * rcp(sq) : 0.0;
   DT<N> r;
   r.v = sq;
 #pragma unroll
@@ -281,9 +299,9 @@ __device__ __forceinline__ void closure_row_s(const DevParams& P, const S* U, S*
 #pragma unroll
   for (int k = 0; k < ND; ++k) F2 = F2 + U[1 + k] * U[1 + k];
   const S cE = P.c * U[0];
-  const S r = 1.0 / smax(F2, cE * cE);
+  const S r = dinv(smax(F2, cE * cE));
   const S f2 = F2 * r;
-  const S h = 1.0 / (2.0 + dsqrt(4.0 - 3.0 * f2));
+  const S h = dinv(2.0 + dsqrt(4.0 - 3.0 * f2));
   const S g = 3.0 * h * r * U[1 + DIR];
 #pragma unroll
   for (int k = 0; k < ND; ++k) Dr[k] = g * U[1 + k] + ((k == DIR) ? (1.0 / 3.0) - f2 * h : mk0<S>(0.0));
@@ -328,9 +346,9 @@ __device__ void source_g(const DevParams& P, const S* z, S rho, S kP, S kF, S kE
   S g = mk0<S>(0.0), iso = mk0<S>(1.0 / 3.0);
   if (P.closure != 1) {
     const S cE = c * E;
-    const S r = 1.0 / smax(F2, cE * cE);
+    const S r = dinv(smax(F2, cE * cE));
     const S f2 = F2 * r;
-    const S h = 1.0 / (2.0 + dsqrt(4.0 - 3.0 * f2));
+    const S h = dinv(2.0 + dsqrt(4.0 - 3.0 * f2));
     g = 3.0 * h * r;
     iso = (1.0 / 3.0) - f2 * h;
   }
@@ -510,33 +528,28 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   um[0] = chc * mu[0] - mu[1 + ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) um[1 + k] = cch * mu[1 + k] - mu[2 + ND + k];
-  Dd zd[M], gd[m];
+  // one 2-tangent evaluation: tangent 0 along kappa_P (with kappa_F when it
+  // aliases kappa_P and has no gradient of its own, and kappa_E = kappa_P through
+  // eP), tangent 1 along kappa_F
+  {
+    DT<2> zd[M], gd[m];
 #pragma unroll
-  for (int i = 0; i < M; ++i) zd[i] = mk(z[i]);
-  if (P.kF_alias) {
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kp, gkF ? 0.0 : 1.0), mk(ke, eP), gd);
-    double g = 0.0;
+    for (int i = 0; i < M; ++i) zd[i] = dtc<2>(z[i]);
+    DT<2> kpd = dtc<2>(kp), kfd = dtc<2>(kf), ked = dtc<2>(ke);
+    kpd.d[0] = 1.0;
+    kfd.d[0] = (P.kF_alias && !gkF) ? 1.0 : 0.0;
+    kfd.d[1] = 1.0;
+    ked.d[0] = eP;
+    source_g<ND, DT<2>>(P, zd, dtc<2>(rq), kpd, kfd, ked, gd);
+    double g = 0.0, h = 0.0;
 #pragma unroll
-    for (int i = 0; i < m; ++i) g += gd[i].d * um[i];
-    gkP[q] += tau * g;
-    if (gkF) {
-      source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kp, 1.0), mk(ke), gd);
-      double h = 0.0;
-#pragma unroll
-      for (int i = 0; i < m; ++i) h += gd[i].d * um[i];
-      gkF[q] += tau * h;
+    for (int i = 0; i < m; ++i) {
+      g += gd[i].d[0] * um[i];
+      h += gd[i].d[1] * um[i];
     }
-  } else {
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp, 1.0), mk(kf), mk(ke, eP), gd);
-    double g = 0.0;
-#pragma unroll
-    for (int i = 0; i < m; ++i) g += gd[i].d * um[i];
     gkP[q] += tau * g;
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf, 1.0), mk(ke), gd);
-    double h = 0.0;
-#pragma unroll
-    for (int i = 0; i < m; ++i) h += gd[i].d * um[i];
-    if (gkF) gkF[q] += tau * h; else gkP[q] += tau * h;
+    if (gkF) gkF[q] += tau * h;
+    else if (!P.kF_alias) gkP[q] += tau * h;
   }
 #pragma unroll
   for (int i = 0; i < M; ++i) lam[i * N + q] = mu[i];
@@ -563,9 +576,9 @@ __device__ __forceinline__ void hll_vjp(const DevParams& P, const double* Um, co
   closure_row_s<ND, DIR, DT<NR>>(P, up, Dp);
   const bool mside = !(Dm[DIR].v < Dp[DIR].v);   // the side max() takes
   const double Dmax = mside ? Dm[DIR].v : Dp[DIR].v;
-  const double sq = sqrt(Dmax);
+  const double sq = sqrt_nonneg(Dmax);
   const double hS = 0.5 * P.chat * sq;
-  const double dhS = sq > 0.0 ? 0.25 * P.chat / sq : 0.0;   // d hS / d D_DD
+  const double dhS = sq > 0.0 ? 0.25 * P.chat * rcp(sq) : 0.0;   // d hS / d D_DD
   double Sig = 0.0;   // sum_r phi_r (U+_r - U-_r)
 #pragma unroll
   for (int r = 0; r < NR; ++r) Sig += phi[r] * (Up[r] - Um[r]);
