@@ -223,62 +223,78 @@ __device__ __forceinline__ void ppm_edges_s(const S& a0, const S& a1, const S& a
   r = a2 + ro;
 }
 
-// Partial derivatives (kl, kr) of the slope slope_s(dl, dr) in its active branch:
-// 0 across an extremum, 1/2 each for the centred slope, 2 for a limiting side.
-__device__ __forceinline__ void slope_partials(double dl, double dr, double& kl, double& kr) {
-  kl = 0.0;
-  kr = 0.0;
-  if (!(dl * dr > 0.0)) return;
-  const double adc = fabs(0.5 * (dl + dr)), adl = 2.0 * fabs(dl), adr = 2.0 * fabs(dr);
+// The same edges as ppm_edges_s<double>, with the branch taken by each step in a
+// byte: bits 0-1, 2-3, 4-5 the cases of the three slopes (0 across an extremum,
+// 1 centred, 2 left-limited, 3 right-limited), bits 6-7 the monotonicity case
+// (0 flattened, 1 l = -2 r, 2 r = -2 l, 3 unchanged). The edges are linear in
+// a0..a4 within a branch, so the code alone fixes their derivatives.
+__device__ __forceinline__ int slope_case(double dl, double dr, double& s) {
+  s = 0.0;
+  if (!(dl * dr > 0.0)) return 0;
+  const double dc = 0.5 * (dl + dr);
+  const double adc = fabs(dc), adl = 2.0 * fabs(dl), adr = 2.0 * fabs(dr);
+  int c;
+  double mag;
   if (adc <= adl && adc <= adr) {
-    kl = 0.5;
-    kr = 0.5;
+    c = 1;
+    mag = adc;
   } else if (adl <= adr) {
-    kl = 2.0;
+    c = 2;
+    mag = adl;
   } else {
-    kr = 2.0;
+    c = 3;
+    mag = adr;
   }
+  s = dc < 0.0 ? -mag : mag;
+  return c;
 }
 
-// Reverse-mode derivative of ppm_edges_s: ga[o] = gl dl/da_o + gr dr/da_o for the
-// edges (l, r) of the middle cell of a0..a4, in the forward's branches (the map is
-// linear within a branch: this is one reverse sweep instead of five tangents).
-__device__ __forceinline__ void ppm_edges_vjp(double a0, double a1, double a2, double a3,
-                                              double a4, double gl, double gr, double* ga) {
+__device__ __forceinline__ unsigned ppm_edges_code(double a0, double a1, double a2, double a3,
+                                                   double a4, double& l, double& r) {
   const double d01 = a1 - a0, d12 = a2 - a1, d23 = a3 - a2, d34 = a4 - a3;
-  const double s1 = slope_s(d01, d12, 0.0), s2 = slope_s(d12, d23, 0.0);
-  const double s3 = slope_s(d23, d34, 0.0);
-  const double lo = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
-  const double ro = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
-  double glo, gro;   // adjoints of the raw offsets through the monotonicity constraint
+  double s1, s2, s3;
+  const unsigned c1 = slope_case(d01, d12, s1);
+  const unsigned c2 = slope_case(d12, d23, s2);
+  const unsigned c3 = slope_case(d23, d34, s3);
+  double lo = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
+  double ro = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
+  unsigned cm;
   if (ro * lo >= 0.0) {
-    glo = 0.0;
-    gro = 0.0;
+    lo = 0.0;
+    ro = 0.0;
+    cm = 0;
   } else {
     const double del = ro - lo;
     const double a6 = -3.0 * (lo + ro);
-    if (del * a6 > del * del) {            // l = a2 - 2 ro, r = a2 + ro
-      glo = 0.0;
-      gro = gr - 2.0 * gl;
-    } else if (del * a6 < -(del * del)) {  // r = a2 - 2 lo, l = a2 + lo
-      glo = gl - 2.0 * gr;
-      gro = 0.0;
+    if (del * a6 > del * del) {
+      lo = (-2.0) * ro;
+      cm = 1;
+    } else if (del * a6 < -(del * del)) {
+      ro = (-2.0) * lo;
+      cm = 2;
     } else {
-      glo = gl;
-      gro = gr;
+      cm = 3;
     }
   }
+  l = a2 + lo;
+  r = a2 + ro;
+  return c1 | (c2 << 2) | (c3 << 4) | (cm << 6);
+}
+
+// ga[o] = gl dl/da_o + gr dr/da_o in the branch recorded by ppm_edges_code
+__device__ __forceinline__ void ppm_vjp_code(unsigned code, double gl, double gr, double* ga) {
+  auto kl = [](unsigned c) { return c == 1 ? 0.5 : (c == 2 ? 2.0 : 0.0); };
+  auto kr = [](unsigned c) { return c == 1 ? 0.5 : (c == 3 ? 2.0 : 0.0); };
+  const unsigned c1 = code & 3u, c2 = (code >> 2) & 3u, c3 = (code >> 4) & 3u, cm = code >> 6;
+  const double glo = (cm == 3) ? gl : (cm == 2 ? gl - 2.0 * gr : 0.0);
+  const double gro = (cm == 3) ? gr : (cm == 1 ? gr - 2.0 * gl : 0.0);
   const double gs1 = (1.0 / 6.0) * glo;
   const double gs2 = (1.0 / 6.0) * (gro - glo);
   const double gs3 = -(1.0 / 6.0) * gro;
-  double k1l, k1r, k2l, k2r, k3l, k3r;
-  slope_partials(d01, d12, k1l, k1r);
-  slope_partials(d12, d23, k2l, k2r);
-  slope_partials(d23, d34, k3l, k3r);
-  const double g01 = k1l * gs1;
-  const double g12 = -0.5 * glo + k1r * gs1 + k2l * gs2;
-  const double g23 = 0.5 * gro + k2r * gs2 + k3l * gs3;
-  const double g34 = k3r * gs3;
+  const double g01 = kl(c1) * gs1;
+  const double g12 = -0.5 * glo + kr(c1) * gs1 + kl(c2) * gs2;
+  const double g23 = 0.5 * gro + kr(c2) * gs2 + kl(c3) * gs3;
+  const double g34 = kr(c3) * gs3;
   ga[0] = -g01;
   ga[1] = g01 - g12;
   ga[2] = g12 - g23 + gl + gr;
@@ -627,11 +643,19 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
        double* __restrict__ out) {
   constexpr int NR = 1 + ND;
   constexpr int TL = TvjpShape<ND>::TL, TP = TvjpShape<ND>::TP;
-  constexpr int NYv = TL + 10, NF = TL + 5, NC = TL + 4;
-  static_assert(NF * TP <= TV_NT && NC * TP <= TV_NT, "one item round per phase");
+  constexpr int NYv = TL + 10, NF = TL + 5, NC = TL + 4, NE = TL + 6;
+  static_assert(NE * TP <= TV_NT && NC * TP <= TV_NT, "one item round per phase");
+  // edge states of the cells next to the faces (local y index e + 2) and their
+  // branch codes; the PPM contributions s_c reuse the edge storage, which is dead
+  // once the face adjoints exist
+  constexpr int NEB = 2 * NR * TP * NE, NCB = 5 * TP * NC;
   __shared__ double s_y[NR][TP][NYv];
   __shared__ double s_fm[2 * NR][TP][NF];
-  __shared__ double s_c[5][TP][NC];
+  __shared__ double s_buf[NEB > NCB ? NEB : NCB];
+  __shared__ unsigned char s_code[NR][TP][NE];
+  double(*s_eL)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_buf);
+  double(*s_eR)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_buf + NR * TP * NE);
+  double(*s_c)[TP][NC] = reinterpret_cast<double(*)[TP][NC]>(s_buf);
 
   const int tid = threadIdx.x;
   const long long N = P.N;
@@ -667,6 +691,22 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
   }
   __syncthreads();
 
+  // ---- PPM edge states and branch codes, once per cell (local y index e + 2) ----
+  if (tid < TP * NE) {
+    const int p = tid / NE, e = tid % NE;
+    if (p0 + p < np) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const double* a = &s_y[r][p][e];
+        double l, rr;
+        s_code[r][p][e] = (unsigned char)ppm_edges_code(a[0], a[1], a[2], a[3], a[4], l, rr);
+        s_eL[r][p][e] = l;
+        s_eR[r][p][e] = rr;
+      }
+    }
+  }
+  __syncthreads();
+
   // ---- face adjoints: face f (local), between cells f-3 and f-2 of the tile ----
   if (tid < TP * NF) {
     const int p = tid / NF, f = tid % NF;
@@ -676,12 +716,8 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         phi[r] = scale * (lam[r * N + qa] - lam[r * N + qb]) * P.inv_dx;
-        const double* a = &s_y[r][p][f];      // cells f-5 .. f: local y index f .. f+5
-        double l, rr;
-        ppm_edges_s<double>(a[0], a[1], a[2], a[3], a[4], l, rr, 0.0);
-        Um[r] = rr;                           // right edge of the cell below the face
-        ppm_edges_s<double>(a[1], a[2], a[3], a[4], a[5], l, rr, 0.0);
-        Up[r] = l;                            // left edge of the cell above it
+        Um[r] = s_eR[r][p][f];                // right edge of the cell below the face
+        Up[r] = s_eL[r][p][f + 1];            // left edge of the cell above it
       }
       double gm[NR], gp[NR];
       hll_vjp<ND, DIR>(P, Um, Up, phi, gm, gp);
@@ -701,9 +737,8 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
       if (p0 + p < np) {
         const double mum = s_fm[r][p][c + 1];      // its right face, w.r.t. aR
         const double mup = s_fm[NR + r][p][c];     // its left face, w.r.t. aL
-        const double* a = &s_y[r][p][c + 1];
         double ga[5];
-        ppm_edges_vjp(a[0], a[1], a[2], a[3], a[4], mup, mum, ga);
+        ppm_vjp_code(s_code[r][p][c + 1], mup, mum, ga);
 #pragma unroll
         for (int o = 0; o < 5; ++o) s_c[o][p][c] = ga[o];
       }
