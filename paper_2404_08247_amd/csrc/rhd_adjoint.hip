@@ -440,15 +440,20 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   // an m x m system instead of the M x M one.
   constexpr int m = 1 + ND;
   const double chc = P.chat_over_c, cch = P.c_chat;
-  double G[m][M];   // column j from a dual evaluation seeded along z_j
+  double G[m][M];   // columns j..j+m-1 from an m-tangent evaluation (M = 2 m)
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    Dd zd[M], gd[m];
+  for (int j = 0; j < M; j += m) {
+    DT<m> zd[M], gd[m];
 #pragma unroll
-    for (int i = 0; i < M; ++i) zd[i] = mk(z[i], i == j ? 1.0 : 0.0);
-    source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), mk(ke), gd);
+    for (int i = 0; i < M; ++i) {
+      zd[i] = dtc<m>(z[i]);
+      if (i >= j && i < j + m) zd[i].d[i - j] = 1.0;
+    }
+    source_g<ND, DT<m>>(P, zd, dtc<m>(rq), dtc<m>(kp), dtc<m>(kf), dtc<m>(ke), gd);
 #pragma unroll
-    for (int i = 0; i < m; ++i) G[i][j] = gd[i].d;
+    for (int i = 0; i < m; ++i)
+#pragma unroll
+      for (int t = 0; t < m; ++t) G[i][j + t] = gd[i].d[t];
   }
   // K[k][i] = delta_ki - tau (G U)[i][k]; (G U)[i][0] = (chat/c) G[i][E] - G[i][Egas],
   // (G U)[i][1+k] = c chat G[i][F_k] - G[i][p_k]; rhs w = U^T lam
