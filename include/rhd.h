@@ -17,6 +17,11 @@
  * eq. numF1 (v_order 1) or eq. numF2 (v_order 2), momentum update, and the outer
  * iteration over the lagged v and F.
  *
+ * Around the radiation step: its hand-written adjoint (rhd_step_adjoint), and the
+ * explicit hydrodynamics that the operator split of Sec. 3.1 runs before it
+ * (rhd_hydro_step, and rhd_rhd_step for the split step with the radiation
+ * subcycled).
+ *
  * Conventions for every entry point
  *  - Array arguments are DEVICE pointers to caller-owned memory (for example
  *    torch tensors on the same GPU); the library never allocates device memory
