@@ -440,30 +440,53 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   // an m x m system instead of the M x M one.
   constexpr int m = 1 + ND;
   const double chc = P.chat_over_c, cch = P.c_chat;
-  double G[m][M];   // columns j..j+m-1 from an m-tangent evaluation (M = 2 m)
+  // G = dg/dz. In 1-D/2-D: columns j..j+m-1 from an m-tangent evaluation (M = 2 m),
+  // held in registers. In 3-D that needs more registers than two waves per SIMD
+  // allow, so there: column j from a dual evaluation seeded along z_j, in a rolled
+  // loop (the values of g are the same in every pass and stay in registers, only the
+  // tangent is evaluated per pass), G in LDS, one slot per thread.
+  constexpr bool GLDS = (ND == 3);
+  __shared__ double s_G[GLDS ? m * M : 1][ATHREADS];
+  double Greg[GLDS ? 1 : m][GLDS ? 1 : M];
+  if constexpr (GLDS) {
+#pragma unroll 1
+    for (int j = 0; j < M; ++j) {
+      Dd zd[M], gd[m];
 #pragma unroll
-  for (int j = 0; j < M; j += m) {
-    DT<m> zd[M], gd[m];
+      for (int i = 0; i < M; ++i) zd[i] = mk(z[i], i == j ? 1.0 : 0.0);
+      source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), mk(ke), gd);
 #pragma unroll
-    for (int i = 0; i < M; ++i) {
-      zd[i] = dtc<m>(z[i]);
-      if (i >= j && i < j + m) zd[i].d[i - j] = 1.0;
+      for (int i = 0; i < m; ++i) s_G[i * M + j][threadIdx.x] = gd[i].d;
     }
-    source_g<ND, DT<m>>(P, zd, dtc<m>(rq), dtc<m>(kp), dtc<m>(kf), dtc<m>(ke), gd);
+  } else {
 #pragma unroll
-    for (int i = 0; i < m; ++i)
+    for (int j = 0; j < M; j += m) {
+      DT<m> zd[M], gd[m];
 #pragma unroll
-      for (int t = 0; t < m; ++t) G[i][j + t] = gd[i].d[t];
+      for (int i = 0; i < M; ++i) {
+        zd[i] = dtc<m>(z[i]);
+        if (i >= j && i < j + m) zd[i].d[i - j] = 1.0;
+      }
+      source_g<ND, DT<m>>(P, zd, dtc<m>(rq), dtc<m>(kp), dtc<m>(kf), dtc<m>(ke), gd);
+#pragma unroll
+      for (int i = 0; i < m; ++i)
+#pragma unroll
+        for (int t = 0; t < m; ++t) Greg[i][j + t] = gd[i].d[t];
+    }
   }
+  auto G = [&](int i, int j) -> double {
+    if constexpr (GLDS) return s_G[i * M + j][threadIdx.x];
+    else return Greg[i][j];
+  };
   // K[k][i] = delta_ki - tau (G U)[i][k]; (G U)[i][0] = (chat/c) G[i][E] - G[i][Egas],
   // (G U)[i][1+k] = c chat G[i][F_k] - G[i][p_k]; rhs w = U^T lam
   double K[m][m], w[m];
 #pragma unroll
   for (int i = 0; i < m; ++i) {
-    K[0][i] = ((i == 0) ? 1.0 : 0.0) - tau * (chc * G[i][0] - G[i][1 + ND]);
+    K[0][i] = ((i == 0) ? 1.0 : 0.0) - tau * (chc * G(i, 0) - G(i, 1 + ND));
 #pragma unroll
     for (int k = 0; k < ND; ++k)
-      K[1 + k][i] = ((i == 1 + k) ? 1.0 : 0.0) - tau * (cch * G[i][1 + k] - G[i][2 + ND + k]);
+      K[1 + k][i] = ((i == 1 + k) ? 1.0 : 0.0) - tau * (cch * G(i, 1 + k) - G(i, 2 + ND + k));
   }
   w[0] = chc * lv[0] - lv[1 + ND];
 #pragma unroll
@@ -540,7 +563,7 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   for (int j = 0; j < M; ++j) {
     double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < m; ++i) acc += G[i][j] * x[i];
+    for (int i = 0; i < m; ++i) acc += G(i, j) * x[i];
     mu[j] = lv[j] + tau * acc;
   }
 
@@ -549,29 +572,45 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   um[0] = chc * mu[0] - mu[1 + ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) um[1 + k] = cch * mu[1 + k] - mu[2 + ND + k];
-  // one 2-tangent evaluation: tangent 0 along kappa_P (with kappa_F when it
-  // aliases kappa_P and has no gradient of its own, and kappa_E = kappa_P through
-  // eP), tangent 1 along kappa_F
-  {
+  // the kappa derivatives: tangent 0 along kappa_P (with kappa_F when it aliases
+  // kappa_P and has no gradient of its own, and kappa_E = kappa_P through eP),
+  // tangent 1 along kappa_F; one 2-tangent evaluation, or in 3-D two dual ones in a
+  // rolled loop (registers, as above)
+  const double kF0 = (P.kF_alias && !gkF) ? 1.0 : 0.0;
+  double gk[2] = {0.0, 0.0};
+  if constexpr (GLDS) {
+#pragma unroll 1
+    for (int t = 0; t < 2; ++t) {
+      Dd zd[M], gd[m];
+#pragma unroll
+      for (int i = 0; i < M; ++i) zd[i] = mk(z[i]);
+      source_g<ND, Dd>(P, zd, mk(rq), mk(kp, t == 0 ? 1.0 : 0.0), mk(kf, t == 0 ? kF0 : 1.0),
+                       mk(ke, t == 0 ? eP : 0.0), gd);
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < m; ++i) acc += gd[i].d * um[i];
+      if (t == 0) gk[0] = acc;
+      else gk[1] = acc;
+    }
+  } else {
     DT<2> zd[M], gd[m];
 #pragma unroll
     for (int i = 0; i < M; ++i) zd[i] = dtc<2>(z[i]);
     DT<2> kpd = dtc<2>(kp), kfd = dtc<2>(kf), ked = dtc<2>(ke);
     kpd.d[0] = 1.0;
-    kfd.d[0] = (P.kF_alias && !gkF) ? 1.0 : 0.0;
+    kfd.d[0] = kF0;
     kfd.d[1] = 1.0;
     ked.d[0] = eP;
     source_g<ND, DT<2>>(P, zd, dtc<2>(rq), kpd, kfd, ked, gd);
-    double g = 0.0, h = 0.0;
 #pragma unroll
     for (int i = 0; i < m; ++i) {
-      g += gd[i].d[0] * um[i];
-      h += gd[i].d[1] * um[i];
+      gk[0] += gd[i].d[0] * um[i];
+      gk[1] += gd[i].d[1] * um[i];
     }
-    gkP[q] += tau * g;
-    if (gkF) gkF[q] += tau * h;
-    else if (!P.kF_alias) gkP[q] += tau * h;
   }
+  gkP[q] += tau * gk[0];
+  if (gkF) gkF[q] += tau * gk[1];
+  else if (!P.kF_alias) gkP[q] += tau * gk[1];
 #pragma unroll
   for (int i = 0; i < M; ++i) lam[i * N + q] = mu[i];
   outputs(mu);
