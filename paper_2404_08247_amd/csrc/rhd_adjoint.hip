@@ -22,8 +22,9 @@
 //      adjoints of its two edge states mu-/mu+ = (dPhi/dU-/+)^T phi (the closure
 //      and its partials from one multi-tangent dual evaluation per side);
 //   2. per cell i: PPM partials of its edge states w.r.t. the 5 stencil values
-//      (5-tangent duals) times mu- of face i+1/2 and mu+ of face i-1/2, giving
-//      its contribution to each of the cells i-2..i+2;
+//      (constants of the limiter branch recorded when the edges were formed)
+//      times mu- of face i+1/2 and mu+ of face i-1/2, giving its contribution
+//      to each of the cells i-2..i+2;
 //   3. per cell j: sum of the contributions addressed to j.
 // Periodic axes only (the library rejects reflecting axes for the adjoint).
 #include "rhd_device.hpp"
@@ -76,7 +77,6 @@ __device__ __forceinline__ Dd dinv(Dd x) { return 1.0 / x; }
 __device__ __forceinline__ double vof(double a) { return a; }
 __device__ __forceinline__ double vof(Dd a) { return a.v; }
 template <typename S> __device__ __forceinline__ S smax(S a, S b) { return vof(a) < vof(b) ? b : a; }
-template <typename S> __device__ __forceinline__ S sabs(S a) { return vof(a) < 0.0 ? -a : a; }
 
 // N-tangent dual (value and N partial derivatives).
 template <int N>
@@ -88,13 +88,6 @@ template <int N> __device__ __forceinline__ DT<N> dtc(double x) {   // constant
   r.v = x;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.d[i] = 0.0;
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> dtseed(double x, int j) {   // d/dx_j = 1
-  DT<N> r;
-  r.v = x;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = (i == j) ? 1.0 : 0.0;
   return r;
 }
 template <int N> __device__ __forceinline__ DT<N> operator+(const DT<N>& a, const DT<N>& b) {
@@ -176,77 +169,27 @@ template <int N> __device__ __forceinline__ DT<N> dsqrt(const DT<N>& a) {
   return r;
 }
 template <int N> __device__ __forceinline__ double vof(const DT<N>& a) { return a.v; }
-template <int N> __device__ __forceinline__ DT<N> sabs(const DT<N>& a) { return a.v < 0.0 ? -a : a; }
 template <> __device__ __forceinline__ DT<3> mk0<DT<3>>(double x) { return dtc<3>(x); }
 template <> __device__ __forceinline__ DT<4> mk0<DT<4>>(double x) { return dtc<4>(x); }
 template <> __device__ __forceinline__ DT<2> mk0<DT<2>>(double x) { return dtc<2>(x); }
 
-// PPM (same method as the forward) on a piecewise-linear scalar type: the
-// tangents of the active branch are carried along.
-template <typename S>
-__device__ __forceinline__ S slope_s(S dl, S dr, S zero) {
-  const S dc = 0.5 * (dl + dr);
-  if (!(vof(dl) * vof(dr) > 0.0)) return zero;
-  const double adc = fabs(vof(dc)), adl = 2.0 * fabs(vof(dl)), adr = 2.0 * fabs(vof(dr));
-  S m;
-  if (adc <= adl && adc <= adr) {
-    m = sabs(dc);
-  } else if (adl <= adr) {
-    m = 2.0 * sabs(dl);
-  } else {
-    m = 2.0 * sabs(dr);
-  }
-  return vof(dc) < 0.0 ? -m : m;
-}
-
-// edge offsets (from the middle value) of the middle cell of a0..a4
-template <typename S>
-__device__ __forceinline__ void ppm_edges_s(const S& a0, const S& a1, const S& a2, const S& a3,
-                                            const S& a4, S& l, S& r, S zero) {
-  const S d01 = a1 - a0, d12 = a2 - a1, d23 = a3 - a2, d34 = a4 - a3;
-  const S s1 = slope_s(d01, d12, zero), s2 = slope_s(d12, d23, zero), s3 = slope_s(d23, d34, zero);
-  S lo = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
-  S ro = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
-  if (vof(ro) * vof(lo) >= 0.0) {
-    lo = zero;
-    ro = zero;
-  } else {
-    const double del = vof(ro) - vof(lo);
-    const double a6 = -3.0 * (vof(lo) + vof(ro));
-    if (del * a6 > del * del) {
-      lo = (-2.0) * ro;
-    } else if (del * a6 < -(del * del)) {
-      ro = (-2.0) * lo;
-    }
-  }
-  l = a2 + lo;
-  r = a2 + ro;
-}
-
-// The same edges as ppm_edges_s<double>, with the branch taken by each step in a
-// byte: bits 0-1, 2-3, 4-5 the cases of the three slopes (0 across an extremum,
-// 1 centred, 2 left-limited, 3 right-limited), bits 6-7 the monotonicity case
-// (0 flattened, 1 l = -2 r, 2 r = -2 l, 3 unchanged). The edges are linear in
-// a0..a4 within a branch, so the code alone fixes their derivatives.
-__device__ __forceinline__ int slope_case(double dl, double dr, double& s) {
-  s = 0.0;
-  if (!(dl * dr > 0.0)) return 0;
-  const double dc = 0.5 * (dl + dr);
-  const double adc = fabs(dc), adl = 2.0 * fabs(dl), adr = 2.0 * fabs(dr);
-  int c;
-  double mag;
-  if (adc <= adl && adc <= adr) {
-    c = 1;
-    mag = adc;
-  } else if (adl <= adr) {
-    c = 2;
-    mag = adl;
-  } else {
-    c = 3;
-    mag = adr;
-  }
-  s = dc < 0.0 ? -mag : mag;
-  return c;
+// PPM edge states of the middle cell of a0..a4 (the forward's method, Sec. 3.3),
+// with the branch taken by each step in a byte: bits 0-1, 2-3, 4-5 the cases of
+// the three MC slopes (0 across an extremum, 1 centred, 2 left-limited, 3
+// right-limited), bits 6-7 the monotonicity case (0 flattened, 1 l = -2 r,
+// 2 r = -2 l, 3 unchanged). The edges are linear in a0..a4 within a branch, so
+// the code alone fixes their derivatives. Ties go to the earlier case in that
+// order, the same choice as the oracle's dual numbers. Branch-free: the lanes of
+// a wave take different cases.
+__device__ __forceinline__ unsigned slope_case(double dl, double dr, double& s) {
+  // sgn(dc) min(|dc|, 2|dl|, 2|dr|), dc = (dl + dr)/2, compared at half scale
+  const double al = fabs(dl), ar = fabs(dr);
+  const double ac = 0.25 * fabs(dl + dr);
+  const double mlr = fmin(al, ar);
+  const unsigned c = (ac <= mlr) ? 1u : (al <= ar ? 2u : 3u);
+  const bool same = dl * dr > 0.0;   // then sgn(dc) = sgn(dl)
+  s = same ? copysign(2.0 * fmin(ac, mlr), dl) : 0.0;
+  return same ? c : 0u;
 }
 
 __device__ __forceinline__ unsigned ppm_edges_code(double a0, double a1, double a2, double a3,
@@ -256,26 +199,16 @@ __device__ __forceinline__ unsigned ppm_edges_code(double a0, double a1, double 
   const unsigned c1 = slope_case(d01, d12, s1);
   const unsigned c2 = slope_case(d12, d23, s2);
   const unsigned c3 = slope_case(d23, d34, s3);
-  double lo = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
-  double ro = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
-  unsigned cm;
-  if (ro * lo >= 0.0) {
-    lo = 0.0;
-    ro = 0.0;
-    cm = 0;
-  } else {
-    const double del = ro - lo;
-    const double a6 = -3.0 * (lo + ro);
-    if (del * a6 > del * del) {
-      lo = (-2.0) * ro;
-      cm = 1;
-    } else if (del * a6 < -(del * del)) {
-      ro = (-2.0) * lo;
-      cm = 2;
-    } else {
-      cm = 3;
-    }
-  }
+  const double lo0 = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
+  const double ro0 = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
+  // CW84 monotonicity: flatten at an extremum, else cap the overshooting side
+  const bool flat = ro0 * lo0 >= 0.0;
+  const double del = ro0 - lo0;
+  const double da = del * (-3.0 * (lo0 + ro0)), dd = del * del;
+  const bool capl = da > dd, capr = da < -dd;   // never both
+  const unsigned cm = flat ? 0u : (capl ? 1u : (capr ? 2u : 3u));
+  const double lo = flat ? 0.0 : (capl ? (-2.0) * ro0 : lo0);
+  const double ro = flat ? 0.0 : (capr ? (-2.0) * lo0 : ro0);
   l = a2 + lo;
   r = a2 + ro;
   return c1 | (c2 << 2) | (c3 << 4) | (cm << 6);
@@ -302,38 +235,57 @@ __device__ __forceinline__ void ppm_vjp_code(unsigned code, double gl, double gr
   ga[4] = g34;
 }
 
-// Row DIR of the closure tensor, D_DIR,k(U) for k < ND, U = (E, F_1..F_ND), on a
-// generic scalar type (same formulas as the forward).
-template <int ND, int DIR, typename S>
-__device__ __forceinline__ void closure_row_s(const DevParams& P, const S* U, S* Dr) {
+// Row DIR of the closure tensor at U = (E, F_1..F_ND) (the forward's formulas)
+// with the partials the HLL adjoint needs, for weights W_k:
+//   Dk[k] = D_DIR,k,   A[j] = sum_k W_k dD_DIR,k/dU_j,   dD[j] = dD_DIR,DIR/dU_j.
+// M1: w = max(|F|^2, (cE)^2), r = 1/w, f2 = |F|^2 r, s = sqrt(4 - 3 f2),
+// h = 1/(2 + s), g = 3 h r F_DIR and D_DIR,k = g F_k + [k = DIR](1/3 - f2 h).
+// Differentiated by hand (exact, the chain rule on these formulas):
+//   df2 = r (d|F|^2 - f2 dw),   dh = h' df2 with h' = 3 h^2/(2 s),
+//   dg = 3 F_DIR (h' r df2 - h r^2 dw) + 3 h r e_DIR,
+//   dD_DIR,k = F_k dg + g e_k - [k = DIR](h + f2 h') df2.
+// Eddington: D = I/3, no partials.
+template <int ND, int DIR>
+__device__ __forceinline__ void closure_row_vjp(const DevParams& P, const double* U,
+                                                const double* W, double* Dk, double* A,
+                                                double* dD) {
   if (P.closure == 1) {
 #pragma unroll
-    for (int k = 0; k < ND; ++k) Dr[k] = (k == DIR) ? mk0<S>(1.0 / 3.0) : mk0<S>(0.0);
+    for (int k = 0; k < ND; ++k) Dk[k] = (k == DIR) ? 1.0 / 3.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j <= ND; ++j) A[j] = dD[j] = 0.0;
     return;
   }
-  S F2 = mk0<S>(0.0);
+  double F2 = 0.0, PF = 0.0;
 #pragma unroll
-  for (int k = 0; k < ND; ++k) F2 = F2 + U[1 + k] * U[1 + k];
-  const S cE = P.c * U[0];
-  const S r = dinv(smax(F2, cE * cE));
-  const S f2 = F2 * r;
-  const S h = dinv(2.0 + dsqrt(4.0 - 3.0 * f2));
-  const S g = 3.0 * h * r * U[1 + DIR];
+  for (int k = 0; k < ND; ++k) {
+    F2 += U[1 + k] * U[1 + k];
+    PF += W[k] * U[1 + k];
+  }
+  const double cE = P.c * U[0];
+  const bool thin = !(F2 < cE * cE);   // the branch max() takes
+  const double r = rcp(thin ? F2 : cE * cE);
+  const double f2 = F2 * r;
+  const double sq = sqrt_1_4(4.0 - 3.0 * f2);
+  const double h = rcp(2.0 + sq);
+  const double FD = U[1 + DIR];
+  const double g = 3.0 * h * r * FD;
+  const double hp = 1.5 * h * h * rcp(sq);
+  const double qp = h + f2 * hp;
+  const double a = 3.0 * FD * hp * r, b = -3.0 * FD * h * r * r;
+  const double wq = W[DIR] * qp;
 #pragma unroll
-  for (int k = 0; k < ND; ++k) Dr[k] = g * U[1 + k] + ((k == DIR) ? (1.0 / 3.0) - f2 * h : mk0<S>(0.0));
-}
-
-// HLL flux along DIR on a generic scalar type (same formulas as the forward).
-template <int ND, int DIR, typename S>
-__device__ void hll_flux_s(const DevParams& P, const S* Um, const S* Up, S* fl) {
-  S Dm[ND], Dp[ND];
-  closure_row_s<ND, DIR, S>(P, Um, Dm);
-  closure_row_s<ND, DIR, S>(P, Up, Dp);
-  const S hS = (0.5 * P.chat) * dsqrt(smax(Dm[DIR], Dp[DIR]));
-  fl[0] = (0.5 * P.chat_over_c) * (Um[1 + DIR] + Up[1 + DIR]) - hS * (Up[0] - Um[0]);
+  for (int j = 0; j <= ND; ++j) {
+    const double dF2 = (j == 0) ? 0.0 : 2.0 * U[j];
+    const double dw = thin ? dF2 : ((j == 0) ? 2.0 * P.c * cE : 0.0);
+    const double df2 = r * (dF2 - f2 * dw);
+    double dg = a * df2 + b * dw;
+    if (j == 1 + DIR) dg += 3.0 * h * r;
+    A[j] = PF * dg - wq * df2 + ((j >= 1) ? g * W[j - 1] : 0.0);
+    dD[j] = FD * dg - qp * df2 + ((j == 1 + DIR) ? g : 0.0);
+  }
 #pragma unroll
-  for (int k = 0; k < ND; ++k)
-    fl[1 + k] = (0.5 * P.c_chat) * (Um[0] * Dm[k] + Up[0] * Dp[k]) - hS * (Up[1 + k] - Um[1 + k]);
+  for (int k = 0; k < ND; ++k) Dk[k] = g * U[1 + k] + ((k == DIR) ? (1.0 / 3.0) - f2 * h : 0.0);
 }
 
 // The mixed-frame four-force terms per cell, z = (E, F_1..F_ND, E_gas, p_1..p_ND):
@@ -620,37 +572,37 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
 //   Phi_0 = (chat/c)(F-_D + F+_D)/2 - hS (E+ - E-),
 //   Phi_1+k = c chat (E- D-_Dk + E+ D+_Dk)/2 - hS (F+_k - F-_k),
 //   hS = chat sqrt(max(D-_DD, D+_DD))/2,
-// with the closure rows and their partials w.r.t. (E, F) of each side from one
-// NR-tangent dual evaluation per side. gm = (dPhi/dU-)^T phi, gp = (dPhi/dU+)^T phi.
+// with the closure rows and their partials w.r.t. (E, F) of each side from
+// closure_row_vjp. gm = (dPhi/dU-)^T phi, gp = (dPhi/dU+)^T phi.
 template <int ND, int DIR>
 __device__ __forceinline__ void hll_vjp(const DevParams& P, const double* Um, const double* Up,
                                         const double* phi, double* gm, double* gp) {
   constexpr int NR = 1 + ND;
-  DT<NR> um[NR], up[NR], Dm[ND], Dp[ND];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    um[r] = dtseed<NR>(Um[r], r);
-    up[r] = dtseed<NR>(Up[r], r);
-  }
-  closure_row_s<ND, DIR, DT<NR>>(P, um, Dm);
-  closure_row_s<ND, DIR, DT<NR>>(P, up, Dp);
-  const bool mside = !(Dm[DIR].v < Dp[DIR].v);   // the side max() takes
-  const double Dmax = mside ? Dm[DIR].v : Dp[DIR].v;
+  const double* W = phi + 1;   // weights of the flux components
+  double Dm[ND], Dp[ND], Am[NR], Ap[NR], dDm[NR], dDp[NR];
+  closure_row_vjp<ND, DIR>(P, Um, W, Dm, Am, dDm);
+  closure_row_vjp<ND, DIR>(P, Up, W, Dp, Ap, dDp);
+  const bool mside = !(Dm[DIR] < Dp[DIR]);   // the side max() takes
+  const double Dmax = mside ? Dm[DIR] : Dp[DIR];
   const double sq = sqrt_nonneg(Dmax);
   const double hS = 0.5 * P.chat * sq;
   const double dhS = sq > 0.0 ? 0.25 * P.chat * rcp(sq) : 0.0;   // d hS / d D_DD
   double Sig = 0.0;   // sum_r phi_r (U+_r - U-_r)
 #pragma unroll
   for (int r = 0; r < NR; ++r) Sig += phi[r] * (Up[r] - Um[r]);
+  double WDm = 0.0, WDp = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    WDm += W[k] * Dm[k];
+    WDp += W[k] * Dp[k];
+  }
   const double hcc = 0.5 * P.c_chat;
+  const double sd = Sig * dhS;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    double tm = 0.0, tp = 0.0;   // sum_k phi_1+k d(E D_Dk)/dU_r on each side
-#pragma unroll
-    for (int k = 0; k < ND; ++k) {
-      tm += phi[1 + k] * (Um[0] * Dm[k].d[r] + (r == 0 ? Dm[k].v : 0.0));
-      tp += phi[1 + k] * (Up[0] * Dp[k].d[r] + (r == 0 ? Dp[k].v : 0.0));
-    }
+    // sum_k phi_1+k d(E D_Dk)/dU_r on each side
+    const double tm = Um[0] * Am[r] + (r == 0 ? WDm : 0.0);
+    const double tp = Up[0] * Ap[r] + (r == 0 ? WDp : 0.0);
     gm[r] = hcc * tm + hS * phi[r];
     gp[r] = hcc * tp - hS * phi[r];
     if (r == 1 + DIR) {
@@ -658,9 +610,9 @@ __device__ __forceinline__ void hll_vjp(const DevParams& P, const double* Um, co
       gp[r] += 0.5 * P.chat_over_c * phi[0];
     }
     if (mside) {
-      gm[r] -= Sig * dhS * Dm[DIR].d[r];
+      gm[r] -= sd * dDm[r];
     } else {
-      gp[r] -= Sig * dhS * Dp[DIR].d[r];
+      gp[r] -= sd * dDp[r];
     }
   }
 }
@@ -675,10 +627,13 @@ __device__ __forceinline__ void hll_vjp(const DevParams& P, const double* Um, co
 //   face f+1/2: phi = scale (lam_{f+1} - lam_f)/dx, mu-+ = (dPhi/dU-+)^T phi;
 //   cell c: C_o = d aR_c/d y_{c+o} mu-_{c+1/2} + d aL_c/d y_{c+o} mu+_{c-1/2};
 //   cell j: out_j += sum_o C_o(j - o).
-template <int ND> struct TvjpShape;
-template <> struct TvjpShape<1> { static constexpr int TL = 256, TP = 1; };
-template <> struct TvjpShape<2> { static constexpr int TL = 32, TP = 8; };
-template <> struct TvjpShape<3> { static constexpr int TL = 32, TP = 8; };
+// Tile shapes: along x the lines are y neighbours and a long tile halves the share
+// of recomputed halo faces; along y and z the lines are x neighbours, and 8 of
+// them keep the staging loads in 64-byte runs.
+template <int ND, int DIR> struct TvjpShape { static constexpr int TL = 32, TP = 8; };
+template <> struct TvjpShape<1, 0> { static constexpr int TL = 256, TP = 1; };
+template <> struct TvjpShape<2, 0> { static constexpr int TL = 64, TP = 4; };
+template <> struct TvjpShape<3, 0> { static constexpr int TL = 64, TP = 4; };
 constexpr int TV_NT = 320;
 
 template <int ND, int DIR>
@@ -686,20 +641,28 @@ __global__ void __launch_bounds__(TV_NT)
 k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam, double scale,
        double* __restrict__ out) {
   constexpr int NR = 1 + ND;
-  constexpr int TL = TvjpShape<ND>::TL, TP = TvjpShape<ND>::TP;
+  constexpr int TL = TvjpShape<ND, DIR>::TL, TP = TvjpShape<ND, DIR>::TP;
   constexpr int NYv = TL + 10, NF = TL + 5, NC = TL + 4, NE = TL + 6;
   static_assert(NE * TP <= TV_NT && NC * TP <= TV_NT, "one item round per phase");
-  // edge states of the cells next to the faces (local y index e + 2) and their
-  // branch codes; the PPM contributions s_c reuse the edge storage, which is dead
-  // once the face adjoints exist
+  // work items of a phase: along x the cells of a line are consecutive in memory
+  // and run fastest; along y and z the lines do, so the global loads and stores
+  // of a wave cover runs of TP consecutive x cells
+  constexpr bool LF = (DIR != 0);
+  // Two LDS regions, each holding what one phase reads and the next one writes:
+  //   A: staged y (edge phase), then the face adjoints (contribution phase);
+  //   B: edge states of the cells next to the faces, local y index e + 2 (face
+  //      phase), then the PPM contributions (gather);
+  // plus the branch codes. A barrier separates every reuse.
+  constexpr int NYB = NR * TP * NYv, NFB = 2 * NR * TP * NF;
   constexpr int NEB = 2 * NR * TP * NE, NCB = 5 * TP * NC;
-  __shared__ double s_y[NR][TP][NYv];
-  __shared__ double s_fm[2 * NR][TP][NF];
-  __shared__ double s_buf[NEB > NCB ? NEB : NCB];
+  __shared__ double s_a[NYB > NFB ? NYB : NFB];
+  __shared__ double s_b[NEB > NCB ? NEB : NCB];
   __shared__ unsigned char s_code[NR][TP][NE];
-  double(*s_eL)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_buf);
-  double(*s_eR)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_buf + NR * TP * NE);
-  double(*s_c)[TP][NC] = reinterpret_cast<double(*)[TP][NC]>(s_buf);
+  double(*s_y)[TP][NYv] = reinterpret_cast<double(*)[TP][NYv]>(s_a);
+  double(*s_fm)[TP][NF] = reinterpret_cast<double(*)[TP][NF]>(s_a);
+  double(*s_eL)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_b);
+  double(*s_eR)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_b + NR * TP * NE);
+  double(*s_c)[TP][NC] = reinterpret_cast<double(*)[TP][NC]>(s_b);
 
   const int tid = threadIdx.x;
   const long long N = P.N;
@@ -726,7 +689,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
 
   // ---- stage y and lam ----
   for (int it = tid; it < TP * NYv; it += TV_NT) {
-    const int p = it / NYv, t = it % NYv;
+    const int p = LF ? it % TP : it / NYv, t = LF ? it / TP : it % NYv;
     if (p0 + p < np) {
       const long long q = cell(wrap(t0 - 5 + t), p);
 #pragma unroll
@@ -737,7 +700,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
 
   // ---- PPM edge states and branch codes, once per cell (local y index e + 2) ----
   if (tid < TP * NE) {
-    const int p = tid / NE, e = tid % NE;
+    const int p = LF ? tid % TP : tid / NE, e = LF ? tid / TP : tid % NE;
     if (p0 + p < np) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -753,7 +716,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
 
   // ---- face adjoints: face f (local), between cells f-3 and f-2 of the tile ----
   if (tid < TP * NF) {
-    const int p = tid / NF, f = tid % NF;
+    const int p = LF ? tid % TP : tid / NF, f = LF ? tid / TP : tid % NF;
     if (p0 + p < np) {
       const long long qb = cell(wrap(t0 - 3 + f), p), qa = cell(wrap(t0 - 2 + f), p);
       double phi[NR], Um[NR], Up[NR];
@@ -777,7 +740,8 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
   // ---- per variable: PPM contributions, then the gather ----
   for (int r = 0; r < NR; ++r) {
     if (tid < TP * NC) {
-      const int p = tid / NC, c = tid % NC;   // cell t0 - 2 + c, local y index c + 3
+      // cell t0 - 2 + c, local y index c + 3
+      const int p = LF ? tid % TP : tid / NC, c = LF ? tid / TP : tid % NC;
       if (p0 + p < np) {
         const double mum = s_fm[r][p][c + 1];      // its right face, w.r.t. aR
         const double mup = s_fm[NR + r][p][c];     // its left face, w.r.t. aL
@@ -789,7 +753,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
     }
     __syncthreads();
     if (tid < TP * TL) {
-      const int p = tid / TL, t = tid % TL;
+      const int p = LF ? tid % TP : tid / TL, t = LF ? tid / TP : tid % TL;
       if (p0 + p < np && t0 + t < na) {
         // cell j = t0 + t receives C_o of cell j - (o - 2), local index t + 4 - o
         double acc = 0.0;
@@ -810,7 +774,7 @@ static unsigned blocks_for(long long n) { return (unsigned)((n + ATHREADS - 1) /
 template <int ND, int DIR>
 static void launch_tvjp(const DevParams& P, const double* y, const double* lam, double scale,
                         double* out, hipStream_t s) {
-  constexpr int TL = TvjpShape<ND>::TL, TP = TvjpShape<ND>::TP;
+  constexpr int TL = TvjpShape<ND, DIR>::TL, TP = TvjpShape<ND, DIR>::TP;
   const int na = P.n[DIR];
   const int np = (ND >= 2) ? P.n[DIR == 0 ? 1 : 0] : 1;
   const int no = (ND == 3) ? P.n[DIR == 2 ? 1 : 2] : 1;
