@@ -11,8 +11,8 @@
 // system r(z) = z - z_in - tau f(z; kappa) = 0, f the mixed-frame four-force
 // terms of eq. G0-G1 in RSLA form, eq. egupdate-fupdate): with A = I - tau df/dz,
 //   lambda_in = A^{-T} lambda_out,   dJ/dkappa += tau (df/dkappa)^T lambda_in.
-// df/dz and df/dkappa are exact: f is evaluated in forward-mode dual numbers
-// seeded along each unknown. The fixed point of the paper's inner/outer iteration
+// df/dz and df/dkappa are exact: the chain rule written out by hand through the
+// intermediates of f (source_jac). The fixed point of the paper's inner/outer iteration
 // is the solution of r(z) = 0 with the closure tensor evaluated at z, so this is
 // the derivative of what the forward step computes (to the outer tolerance).
 //
@@ -20,7 +20,7 @@
 // per axis d, staged in LDS:
 //   1. per face i+1/2: phi = dJ/dPhi = (lambda_{i+1} - lambda_i)/dx, and the
 //      adjoints of its two edge states mu-/mu+ = (dPhi/dU-/+)^T phi (the closure
-//      and its partials from one multi-tangent dual evaluation per side);
+//      row and its partials, differentiated by hand, per side);
 //   2. per cell i: PPM partials of its edge states w.r.t. the 5 stencil values
 //      (constants of the limiter branch recorded when the edges were formed)
 //      times mu- of face i+1/2 and mu+ of face i-1/2, giving its contribution
@@ -32,146 +32,6 @@
 namespace rhd {
 
 constexpr int ATHREADS = 256;
-
-// ---------------------------------------------------------------------------
-// Scalar types: double, a one-tangent dual, and a five-tangent dual.
-// Comparisons, min/max and sign decisions use the value only.
-// ---------------------------------------------------------------------------
-struct Dd {
-  double v, d;
-};
-template <typename S> __device__ __forceinline__ S mk0(double x);
-template <> __device__ __forceinline__ double mk0<double>(double x) { return x; }
-template <> __device__ __forceinline__ Dd mk0<Dd>(double x) { return Dd{x, 0.0}; }
-__device__ __forceinline__ Dd mk(double v, double d = 0.0) { return Dd{v, d}; }
-__device__ __forceinline__ Dd operator+(Dd a, Dd b) { return mk(a.v + b.v, a.d + b.d); }
-__device__ __forceinline__ Dd operator-(Dd a, Dd b) { return mk(a.v - b.v, a.d - b.d); }
-__device__ __forceinline__ Dd operator-(Dd a) { return mk(-a.v, -a.d); }
-__device__ __forceinline__ Dd operator*(Dd a, Dd b) { return mk(a.v * b.v, a.d * b.v + a.v * b.d); }
-__device__ __forceinline__ Dd operator*(double a, Dd b) { return mk(a * b.v, a * b.d); }
-__device__ __forceinline__ Dd operator*(Dd a, double b) { return mk(a.v * b, a.d * b); }
-__device__ __forceinline__ Dd operator+(Dd a, double b) { return mk(a.v + b, a.d); }
-__device__ __forceinline__ Dd operator+(double a, Dd b) { return mk(a + b.v, b.d); }
-__device__ __forceinline__ Dd operator-(double a, Dd b) { return mk(a - b.v, -b.d); }
-__device__ __forceinline__ Dd operator-(Dd a, double b) { return mk(a.v - b, a.d); }
-// Quotients and square roots of the derivative types use the refined hardware
-// reciprocal and square root (rhd_device.hpp): they feed derivatives only.
-__device__ __forceinline__ Dd operator/(Dd a, Dd b) {
-  const double ib = rcp(b.v);
-  const double q = a.v * ib;
-  return mk(q, (a.d - q * b.d) * ib);
-}
-__device__ __forceinline__ Dd operator/(double a, Dd b) {
-  const double ib = rcp(b.v);
-  const double q = a * ib;
-  return mk(q, -q * b.d * ib);
-}
-__device__ __forceinline__ Dd dsqrt(Dd a) {
-  const double s = sqrt_nonneg(a.v);
-  return mk(s, s > 0.0 ? a.d * (0.5 * rcp(s)) : 0.0);
-}
-__device__ __forceinline__ double dsqrt(double a) { return sqrt_nonneg(a); }
-// 1/x on double or a derivative type
-__device__ __forceinline__ double dinv(double x) { return rcp(x); }
-__device__ __forceinline__ Dd dinv(Dd x) { return 1.0 / x; }
-__device__ __forceinline__ double vof(double a) { return a; }
-__device__ __forceinline__ double vof(Dd a) { return a.v; }
-template <typename S> __device__ __forceinline__ S smax(S a, S b) { return vof(a) < vof(b) ? b : a; }
-
-// N-tangent dual (value and N partial derivatives).
-template <int N>
-struct DT {
-  double v, d[N];
-};
-template <int N> __device__ __forceinline__ DT<N> dtc(double x) {   // constant
-  DT<N> r;
-  r.v = x;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = 0.0;
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator+(const DT<N>& a, const DT<N>& b) {
-  DT<N> r;
-  r.v = a.v + b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i];
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator-(const DT<N>& a, const DT<N>& b) {
-  DT<N> r;
-  r.v = a.v - b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i];
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator-(const DT<N>& a) {
-  DT<N> r;
-  r.v = -a.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i];
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator*(double a, const DT<N>& b) {
-  DT<N> r;
-  r.v = a * b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a * b.d[i];
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator*(const DT<N>& a, double b) {
-  return b * a;
-}
-template <int N> __device__ __forceinline__ DT<N> operator*(const DT<N>& a, const DT<N>& b) {
-  DT<N> r;
-  r.v = a.v * b.v;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i];
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator+(const DT<N>& a, double b) {
-  DT<N> r = a;
-  r.v += b;
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator+(double a, const DT<N>& b) {
-  return b + a;
-}
-template <int N> __device__ __forceinline__ DT<N> operator-(double a, const DT<N>& b) {
-  return (-b) + a;
-}
-template <int N> __device__ __forceinline__ DT<N> operator/(double a, const DT<N>& b) {
-  const double ib = rcp(b.v);
-  const double q = a * ib;
-  const double s = -q * ib;
-  DT<N> r;
-  r.v = q;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = s * b.d[i];
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> operator/(const DT<N>& a, const DT<N>& b) {
-  const double ib = rcp(b.v);
-  const double q = a.v * ib;
-  DT<N> r;
-  r.v = q;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - q * b.d[i]) * ib;
-  return r;
-}
-template <int N> __device__ __forceinline__ DT<N> dinv(const DT<N>& x) { return 1.0 / x; }
-template <int N> __device__ __forceinline__ DT<N> dsqrt(const DT<N>& a) {
-  const double sq = sqrt_nonneg(a.v);
-  const double f = sq > 0.0 ? 0.5 * rcp(sq) : 0.0;
-  DT<N> r;
-  r.v = sq;
-#pragma unroll
-  for (int i = 0; i < N; ++i) r.d[i] = f * a.d[i];
-  return r;
-}
-template <int N> __device__ __forceinline__ double vof(const DT<N>& a) { return a.v; }
-template <> __device__ __forceinline__ DT<3> mk0<DT<3>>(double x) { return dtc<3>(x); }
-template <> __device__ __forceinline__ DT<4> mk0<DT<4>>(double x) { return dtc<4>(x); }
-template <> __device__ __forceinline__ DT<2> mk0<DT<2>>(double x) { return dtc<2>(x); }
 
 // PPM edge states of the middle cell of a0..a4 (the forward's method, Sec. 3.3),
 // with the branch taken by each step in a byte: bits 0-1, 2-3, 4-5 the cases of
@@ -292,66 +152,139 @@ __device__ __forceinline__ void closure_row_vjp(const DevParams& P, const double
 // g = (-c G0, -G_1..-G_ND) from eq. G0-G1 (order 2; order 1 keeps the O(v/c)
 // terms), P = D(E, F) E. The source terms are f = U g with the constant map
 //   f_E = (chat/c) g_0, f_Egas = -g_0, f_F_k = c chat g_k, f_p_k = -g_k
-// (eq. egupdate-fupdate in RSLA form).
-template <int ND, typename S>
-__device__ void source_g(const DevParams& P, const S* z, S rho, S kP, S kF, S kE, S* gout) {
-  const double c = P.c;
-  const S chiP = rho * kP, chiE = rho * kE, chiF = rho * kF;
-  const S E = z[0], Eg = z[1 + ND];
-  S v[ND];
-  S v2 = mk0<S>(0.0), vF = mk0<S>(0.0), F2 = mk0<S>(0.0);
+// (eq. egupdate-fupdate in RSLA form). With v = p/rho, T = (E_gas - rho v^2/2)/(rho c_v),
+// B = a_r T^4, b2 = v^2/c^2, Dv = D v = iso v + gc F (v.F) and vDv = v.D v, where the
+// closure is D = iso I + gc F F^T (M1: gc = 3 h r, iso = 1/3 - f2 h as in the
+// forward; Eddington: gc = 0, iso = 1/3):
+//   order 2, hb = 1 + b2/2, L = E - 2 (v.F)/c^2:
+//     g_0 = c (chiP B - chiE E) hb + (2 chiE - chiF)(v.F)/c + c (chiF - chiE)(b2 E + E vDv/c^2)
+//     g_k = (-chiF F_k hb + chiP B v_k + chiF E Dv_k + (chiF - chiE) L v_k)/c
+//   order 1: hb = 1, L = E and no (chiF - chiE) term in g_0.
+// g is linear in the opacities, g = chiP aP + chiF aF + chiE aE, which gives its
+// opacity derivatives. source_jac returns those coefficients and G = dg/dz (m x M,
+// m = 1 + ND, M = 2 + 2 ND), differentiated by hand (the chain rule through the
+// intermediates above, whose partials are sparse: v and b2 depend on p only, T on
+// E_gas and p, the closure scalars on E and F).
+template <int ND>
+__device__ __forceinline__ void source_jac(const DevParams& P, const double* z, double rho,
+                                           double chiP, double chiF, double chiE,
+                                           double (*G)[2 + 2 * ND], double* aP, double* aF,
+                                           double* aE) {
+  constexpr int m = 1 + ND;
+  const double c = P.c, ic = 1.0 / P.c, ic2 = P.inv_c2;
+  const double dchi = chiF - chiE;
+  const double ir = rcp(rho);
+  const double E = z[0], Eg = z[1 + ND];
+  const double* F = z + 1;
+  double v[ND];
+  double v2 = 0.0, vF = 0.0, F2 = 0.0;
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
-    v[k] = z[2 + ND + k] / rho;
-    v2 = v2 + v[k] * v[k];
-    vF = vF + v[k] * z[1 + k];
-    F2 = F2 + z[1 + k] * z[1 + k];
+    v[k] = z[2 + ND + k] * ir;
+    v2 += v[k] * v[k];
+    vF += v[k] * F[k];
+    F2 += F[k] * F[k];
   }
-  const S b2 = v2 * P.inv_c2;
-  const S T = (Eg - 0.5 * rho * v2) / (rho * P.cv_mass);
-  const S T2 = T * T;
-  const S B = P.a_r * (T2 * T2);
-  S g = mk0<S>(0.0), iso = mk0<S>(1.0 / 3.0);
+  const double b2 = v2 * ic2;
+  const double iT = rcp(rho * P.cv_mass);
+  const double T = (Eg - 0.5 * rho * v2) * iT;
+  const double T2 = T * T;
+  const double B = P.a_r * (T2 * T2);
+  const double dBE = 4.0 * P.a_r * T2 * T * iT;   // dB/dE_gas; dB/dp_j = -dBE v_j
+  // closure scalars and their partials over (E, F_1..F_ND) (as in closure_row_vjp)
+  double gc = 0.0, iso = 1.0 / 3.0, dgc[m], diso[m];
+#pragma unroll
+  for (int j = 0; j < m; ++j) dgc[j] = diso[j] = 0.0;
   if (P.closure != 1) {
-    const S cE = c * E;
-    const S r = dinv(smax(F2, cE * cE));
-    const S f2 = F2 * r;
-    const S h = dinv(2.0 + dsqrt(4.0 - 3.0 * f2));
-    g = 3.0 * h * r;
+    const double cE = c * E;
+    const bool thin = !(F2 < cE * cE);
+    const double r = rcp(thin ? F2 : cE * cE);
+    const double f2 = F2 * r;
+    const double sq = sqrt_1_4(4.0 - 3.0 * f2);
+    const double h = rcp(2.0 + sq);
+    gc = 3.0 * h * r;
     iso = (1.0 / 3.0) - f2 * h;
+    const double hp = 1.5 * h * h * rcp(sq);
+    const double qp = h + f2 * hp;
+#pragma unroll
+    for (int j = 0; j < m; ++j) {
+      const double dF2 = (j == 0) ? 0.0 : 2.0 * F[j - 1];
+      const double dw = thin ? dF2 : ((j == 0) ? 2.0 * c * cE : 0.0);
+      const double df2 = r * (dF2 - f2 * dw);
+      dgc[j] = 3.0 * (hp * r * df2 - h * r * r * dw);
+      diso[j] = -qp * df2;
+    }
   }
-  S Dv[ND];
+  double Dv[ND];
 #pragma unroll
-  for (int k = 0; k < ND; ++k) Dv[k] = iso * v[k] + g * z[1 + k] * vF;
-  const S vDv = iso * v2 + g * vF * vF;
-  S mcG0, mG[ND];
-  if (P.v_order == 2) {
-    const S hb = 1.0 + 0.5 * b2;
-    mcG0 = c * (chiP * B - chiE * E) * hb + (2.0 * chiE - chiF) * vF * (1.0 / c) +
-           c * (chiF - chiE) * (b2 * E + E * vDv * P.inv_c2);
+  for (int k = 0; k < ND; ++k) Dv[k] = iso * v[k] + gc * F[k] * vF;
+  const double vDv = iso * v2 + gc * vF * vF;
+  const bool o2 = (P.v_order == 2);
+  const double hb = o2 ? 1.0 + 0.5 * b2 : 1.0;
+  const double L = o2 ? E - 2.0 * vF * ic2 : E;
+  const double Q = o2 ? b2 * E + E * vDv * ic2 : 0.0;   // order-2 bracket of g_0
+  const double a1 = (2.0 * chiE - chiF) * ic;
+
+  // column E
+  {
+    const double dvDv = diso[0] * v2 + dgc[0] * vF * vF;
+    G[0][0] = -c * chiE * hb + (o2 ? c * dchi * (b2 + vDv * ic2 + E * dvDv * ic2) : 0.0);
 #pragma unroll
-    for (int k = 0; k < ND; ++k)
-      mG[k] = (-1.0 / c) * chiF * z[1 + k] * hb + (1.0 / c) * chiP * B * v[k] +
-              (1.0 / c) * chiF * E * Dv[k] +
-              (1.0 / c) * (chiF - chiE) * (E - 2.0 * vF * P.inv_c2) * v[k];
-  } else {
-    mcG0 = c * (chiP * B - chiE * E) + (2.0 * chiE - chiF) * vF * (1.0 / c);
-#pragma unroll
-    for (int k = 0; k < ND; ++k)
-      mG[k] = (-1.0 / c) * chiF * z[1 + k] + (1.0 / c) * chiP * B * v[k] +
-              (1.0 / c) * chiF * E * Dv[k] + (1.0 / c) * (chiF - chiE) * E * v[k];
+    for (int k = 0; k < ND; ++k) {
+      const double dDv = diso[0] * v[k] + dgc[0] * F[k] * vF;
+      G[1 + k][0] = ic * (chiF * Dv[k] + chiF * E * dDv + dchi * v[k]);
+    }
   }
-  gout[0] = mcG0;
+  // columns F_j
 #pragma unroll
-  for (int k = 0; k < ND; ++k) gout[1 + k] = mG[k];
+  for (int j = 0; j < ND; ++j) {
+    const double dvDv = diso[1 + j] * v2 + dgc[1 + j] * vF * vF + 2.0 * gc * vF * v[j];
+    G[0][1 + j] = a1 * v[j] + (o2 ? c * dchi * E * dvDv * ic2 : 0.0);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      const double dDv = diso[1 + j] * v[k] + dgc[1 + j] * F[k] * vF + (k == j ? gc * vF : 0.0) +
+                         gc * F[k] * v[j];
+      G[1 + k][1 + j] = ic * ((k == j ? -chiF * hb : 0.0) + chiF * E * dDv +
+                              (o2 ? -2.0 * dchi * v[j] * ic2 * v[k] : 0.0));
+    }
+  }
+  // column E_gas
+  G[0][1 + ND] = c * chiP * dBE * hb;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) G[1 + k][1 + ND] = ic * chiP * dBE * v[k];
+  // columns p_j
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    const double dBp = -dBE * v[j];
+    const double dvDv = 2.0 * (iso * v[j] + gc * vF * F[j]) * ir;
+    if (o2) {
+      const double db2 = 2.0 * v[j] * ir * ic2;
+      G[0][2 + ND + j] = c * chiP * dBp * hb + 0.5 * c * (chiP * B - chiE * E) * db2 +
+                         a1 * F[j] * ir + c * dchi * (db2 * E + E * dvDv * ic2);
+    } else {
+      G[0][2 + ND + j] = c * chiP * dBp + a1 * F[j] * ir;
+    }
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      const double dDv = ((k == j ? iso : 0.0) + gc * F[k] * F[j]) * ir;
+      double t = chiP * (dBp * v[k] + (k == j ? B * ir : 0.0)) + chiF * E * dDv +
+                 (k == j ? dchi * L * ir : 0.0);
+      if (o2) t += -chiF * F[k] * v[j] * ir * ic2 - 2.0 * dchi * F[j] * ir * ic2 * v[k];
+      G[1 + k][2 + ND + j] = ic * t;
+    }
+  }
+  // opacity coefficients
+  aP[0] = c * B * hb;
+  aF[0] = -vF * ic + c * Q;
+  aE[0] = -c * E * hb + 2.0 * vF * ic - c * Q;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    aP[1 + k] = B * v[k] * ic;
+    aF[1 + k] = (-F[k] * hb + E * Dv[k] + L * v[k]) * ic;
+    aE[1 + k] = -L * v[k] * ic;
+  }
 }
 
-// ---------------------------------------------------------------------------
-// Kernels
-// ---------------------------------------------------------------------------
-// Src adjoint: mu = A^{-T} lam at the converged cell state z, written back to lam;
-// g_kappa += tau (df/dkappa)^T mu; and the vector updates that follow it in the
-// reverse step: o1 = a1 mu (if o1), o2 = a2 mu + b2 o2 (if o2).
 template <int ND>
 __global__ void __launch_bounds__(ATHREADS)
 k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
@@ -392,44 +325,10 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   // an m x m system instead of the M x M one.
   constexpr int m = 1 + ND;
   const double chc = P.chat_over_c, cch = P.c_chat;
-  // G = dg/dz. In 1-D/2-D: columns j..j+m-1 from an m-tangent evaluation (M = 2 m),
-  // held in registers. In 3-D that needs more registers than two waves per SIMD
-  // allow, so there: column j from a dual evaluation seeded along z_j, in a rolled
-  // loop (the values of g are the same in every pass and stay in registers, only the
-  // tangent is evaluated per pass), G in LDS, one slot per thread.
-  constexpr bool GLDS = (ND == 3);
-  __shared__ double s_G[GLDS ? m * M : 1][ATHREADS];
-  double Greg[GLDS ? 1 : m][GLDS ? 1 : M];
-  if constexpr (GLDS) {
-#pragma unroll 1
-    for (int j = 0; j < M; ++j) {
-      Dd zd[M], gd[m];
-#pragma unroll
-      for (int i = 0; i < M; ++i) zd[i] = mk(z[i], i == j ? 1.0 : 0.0);
-      source_g<ND, Dd>(P, zd, mk(rq), mk(kp), mk(kf), mk(ke), gd);
-#pragma unroll
-      for (int i = 0; i < m; ++i) s_G[i * M + j][threadIdx.x] = gd[i].d;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < M; j += m) {
-      DT<m> zd[M], gd[m];
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        zd[i] = dtc<m>(z[i]);
-        if (i >= j && i < j + m) zd[i].d[i - j] = 1.0;
-      }
-      source_g<ND, DT<m>>(P, zd, dtc<m>(rq), dtc<m>(kp), dtc<m>(kf), dtc<m>(ke), gd);
-#pragma unroll
-      for (int i = 0; i < m; ++i)
-#pragma unroll
-        for (int t = 0; t < m; ++t) Greg[i][j + t] = gd[i].d[t];
-    }
-  }
-  auto G = [&](int i, int j) -> double {
-    if constexpr (GLDS) return s_G[i * M + j][threadIdx.x];
-    else return Greg[i][j];
-  };
+  // G = dg/dz and the opacity coefficients of g, in registers
+  double Gm[m][M], aP[m], aF[m], aE[m];
+  source_jac<ND>(P, z, rq, rq * kp, rq * kf, rq * ke, Gm, aP, aF, aE);
+  auto G = [&](int i, int j) -> double { return Gm[i][j]; };
   // K[k][i] = delta_ki - tau (G U)[i][k]; (G U)[i][0] = (chat/c) G[i][E] - G[i][Egas],
   // (G U)[i][1+k] = c chat G[i][F_k] - G[i][p_k]; rhs w = U^T lam
   double K[m][m], w[m];
@@ -524,41 +423,16 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   um[0] = chc * mu[0] - mu[1 + ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) um[1 + k] = cch * mu[1 + k] - mu[2 + ND + k];
-  // the kappa derivatives: tangent 0 along kappa_P (with kappa_F when it aliases
-  // kappa_P and has no gradient of its own, and kappa_E = kappa_P through eP),
-  // tangent 1 along kappa_F; one 2-tangent evaluation, or in 3-D two dual ones in a
-  // rolled loop (registers, as above)
+  // the opacity derivatives of g = chiP aP + chiF aF + chiE aE, chi = rho kappa:
+  // gk[0] along kappa_P (with kappa_F when it aliases kappa_P and has no gradient of
+  // its own, and kappa_E = kappa_P unless a separate kappa_E is held fixed),
+  // gk[1] along kappa_F
   const double kF0 = (P.kF_alias && !gkF) ? 1.0 : 0.0;
   double gk[2] = {0.0, 0.0};
-  if constexpr (GLDS) {
-#pragma unroll 1
-    for (int t = 0; t < 2; ++t) {
-      Dd zd[M], gd[m];
 #pragma unroll
-      for (int i = 0; i < M; ++i) zd[i] = mk(z[i]);
-      source_g<ND, Dd>(P, zd, mk(rq), mk(kp, t == 0 ? 1.0 : 0.0), mk(kf, t == 0 ? kF0 : 1.0),
-                       mk(ke, t == 0 ? eP : 0.0), gd);
-      double acc = 0.0;
-#pragma unroll
-      for (int i = 0; i < m; ++i) acc += gd[i].d * um[i];
-      if (t == 0) gk[0] = acc;
-      else gk[1] = acc;
-    }
-  } else {
-    DT<2> zd[M], gd[m];
-#pragma unroll
-    for (int i = 0; i < M; ++i) zd[i] = dtc<2>(z[i]);
-    DT<2> kpd = dtc<2>(kp), kfd = dtc<2>(kf), ked = dtc<2>(ke);
-    kpd.d[0] = 1.0;
-    kfd.d[0] = kF0;
-    kfd.d[1] = 1.0;
-    ked.d[0] = eP;
-    source_g<ND, DT<2>>(P, zd, dtc<2>(rq), kpd, kfd, ked, gd);
-#pragma unroll
-    for (int i = 0; i < m; ++i) {
-      gk[0] += gd[i].d[0] * um[i];
-      gk[1] += gd[i].d[1] * um[i];
-    }
+  for (int i = 0; i < m; ++i) {
+    gk[0] += rq * (aP[i] + kF0 * aF[i] + eP * aE[i]) * um[i];
+    gk[1] += rq * aF[i] * um[i];
   }
   gkP[q] += tau * gk[0];
   if (gkF) gkF[q] += tau * gk[1];
@@ -644,9 +518,11 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
   constexpr int TL = TvjpShape<ND, DIR>::TL, TP = TvjpShape<ND, DIR>::TP;
   constexpr int NYv = TL + 10, NF = TL + 5, NC = TL + 4, NE = TL + 6;
   static_assert(NE * TP <= TV_NT && NC * TP <= TV_NT, "one item round per phase");
-  // work items of a phase: along x the cells of a line are consecutive in memory
+  // Work items of a phase: along x the cells of a line are consecutive in memory
   // and run fastest; along y and z the lines do, so the global loads and stores
-  // of a wave cover runs of TP consecutive x cells
+  // of a wave cover runs of TP consecutive x cells. The LDS arrays follow the
+  // same order (index [..][p][t] along x, [..][t][p] along y and z), so a wave's
+  // LDS accesses are consecutive words.
   constexpr bool LF = (DIR != 0);
   // Two LDS regions, each holding what one phase reads and the next one writes:
   //   A: staged y (edge phase), then the face adjoints (contribution phase);
@@ -657,12 +533,17 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
   constexpr int NEB = 2 * NR * TP * NE, NCB = 5 * TP * NC;
   __shared__ double s_a[NYB > NFB ? NYB : NFB];
   __shared__ double s_b[NEB > NCB ? NEB : NCB];
-  __shared__ unsigned char s_code[NR][TP][NE];
-  double(*s_y)[TP][NYv] = reinterpret_cast<double(*)[TP][NYv]>(s_a);
-  double(*s_fm)[TP][NF] = reinterpret_cast<double(*)[TP][NF]>(s_a);
-  double(*s_eL)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_b);
-  double(*s_eR)[TP][NE] = reinterpret_cast<double(*)[TP][NE]>(s_b + NR * TP * NE);
-  double(*s_c)[TP][NC] = reinterpret_cast<double(*)[TP][NC]>(s_b);
+  __shared__ unsigned char s_code[NR * TP * NE];
+  // index of (array k, line p, position t) in an array set of length L per line
+  auto at = [](int k, int p, int t, int L) {
+    return LF ? (k * L + t) * TP + p : (k * TP + p) * L + t;
+  };
+  constexpr int TS = LF ? TP : 1;   // LDS stride between neighbours along the line
+  double* s_y = s_a;                // [NR] x NYv, cells t0-5+t
+  double* s_fm = s_a;               // [2 NR] x NF: mu- (k < NR), mu+ (k >= NR)
+  double* s_eL = s_b;               // [NR] x NE
+  double* s_eR = s_b + NR * TP * NE;
+  double* s_c = s_b;                // [5] x NC
 
   const int tid = threadIdx.x;
   const long long N = P.N;
@@ -675,9 +556,31 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
   const long long sp = (pax == 0) ? 1 : (long long)nx;
   // the remaining axis (3-D): z for DIR 0/1, y for DIR 2
   const long long so = (ND == 3) ? ((DIR == 2) ? (long long)nx : (long long)nx * ny) : 0;
-  const int t0 = blockIdx.x * TL;
-  const int p0 = blockIdx.y * TP;
-  const long long obase = (long long)blockIdx.z * so;
+  // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+  // Renumber them so that each XCD gets a contiguous run of tiles, in the order
+  // in which neighbours share cache lines: along x the tiles of a line (they
+  // share halo cells), along y and z the line blocks (TP doubles are half a
+  // 128-byte line).
+  int bt = blockIdx.x, bp = blockIdx.y, bo = blockIdx.z;
+  {
+    const int gt = gridDim.x, gp = gridDim.y;
+    const int nb = gt * gp * gridDim.z;
+    if ((nb % 8) == 0) {
+      const int lin = (blockIdx.z * gp + blockIdx.y) * gt + blockIdx.x;
+      const int lid = (lin % 8) * (nb / 8) + lin / 8;
+      if (LF) {
+        bp = lid % gp;
+        bt = (lid / gp) % gt;
+      } else {
+        bt = lid % gt;
+        bp = (lid / gt) % gp;
+      }
+      bo = lid / (gt * gp);
+    }
+  }
+  const int t0 = bt * TL;
+  const int p0 = bp * TP;
+  const long long obase = (long long)bo * so;
   auto cell = [&](int a, int p) {   // a wrapped into [0, na)
     return obase + (long long)a * sa + (long long)(p0 + p) * sp;
   };
@@ -686,29 +589,37 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
     while (a >= na) a -= na;
     return a;
   };
+  // line and position of work item i of a phase with L positions per line
+  auto item = [](int i, int L, int& p, int& t) {
+    p = LF ? i % TP : i / L;
+    t = LF ? i / TP : i % L;
+  };
 
-  // ---- stage y and lam ----
+  // ---- stage y ----
   for (int it = tid; it < TP * NYv; it += TV_NT) {
-    const int p = LF ? it % TP : it / NYv, t = LF ? it / TP : it % NYv;
+    int p, t;
+    item(it, NYv, p, t);
     if (p0 + p < np) {
       const long long q = cell(wrap(t0 - 5 + t), p);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) s_y[r][p][t] = y[r * N + q];
+      for (int r = 0; r < NR; ++r) s_y[at(r, p, t, NYv)] = y[r * N + q];
     }
   }
   __syncthreads();
 
   // ---- PPM edge states and branch codes, once per cell (local y index e + 2) ----
   if (tid < TP * NE) {
-    const int p = LF ? tid % TP : tid / NE, e = LF ? tid / TP : tid % NE;
+    int p, e;
+    item(tid, NE, p, e);
     if (p0 + p < np) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        const double* a = &s_y[r][p][e];
+        const double* a = &s_y[at(r, p, e, NYv)];
         double l, rr;
-        s_code[r][p][e] = (unsigned char)ppm_edges_code(a[0], a[1], a[2], a[3], a[4], l, rr);
-        s_eL[r][p][e] = l;
-        s_eR[r][p][e] = rr;
+        s_code[at(r, p, e, NE)] =
+            (unsigned char)ppm_edges_code(a[0], a[TS], a[2 * TS], a[3 * TS], a[4 * TS], l, rr);
+        s_eL[at(r, p, e, NE)] = l;
+        s_eR[at(r, p, e, NE)] = rr;
       }
     }
   }
@@ -716,53 +627,65 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
 
   // ---- face adjoints: face f (local), between cells f-3 and f-2 of the tile ----
   if (tid < TP * NF) {
-    const int p = LF ? tid % TP : tid / NF, f = LF ? tid / TP : tid % NF;
+    int p, f;
+    item(tid, NF, p, f);
     if (p0 + p < np) {
       const long long qb = cell(wrap(t0 - 3 + f), p), qa = cell(wrap(t0 - 2 + f), p);
       double phi[NR], Um[NR], Up[NR];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         phi[r] = scale * (lam[r * N + qa] - lam[r * N + qb]) * P.inv_dx;
-        Um[r] = s_eR[r][p][f];                // right edge of the cell below the face
-        Up[r] = s_eL[r][p][f + 1];            // left edge of the cell above it
+        Um[r] = s_eR[at(r, p, f, NE)];        // right edge of the cell below the face
+        Up[r] = s_eL[at(r, p, f + 1, NE)];    // left edge of the cell above it
       }
       double gm[NR], gp[NR];
       hll_vjp<ND, DIR>(P, Um, Up, phi, gm, gp);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        s_fm[r][p][f] = gm[r];
-        s_fm[NR + r][p][f] = gp[r];
+        s_fm[at(r, p, f, NF)] = gm[r];
+        s_fm[at(NR + r, p, f, NF)] = gp[r];
       }
     }
   }
   __syncthreads();
 
-  // ---- per variable: PPM contributions, then the gather ----
+  // ---- per variable: PPM contributions, then the gather into registers; the
+  // own cells' outputs are loaded first and stored once at the end, so the loop
+  // waits on no global load ----
+  int gpi, gti;   // gather item: line and cell of the tile
+  item(tid, TL, gpi, gti);
+  const bool gown = tid < TP * TL && p0 + gpi < np && t0 + gti < na;
+  const long long gq = gown ? cell(t0 + gti, gpi) : 0;
+  double acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = gown ? out[r * N + gq] : 0.0;
+#pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (tid < TP * NC) {
-      // cell t0 - 2 + c, local y index c + 3
-      const int p = LF ? tid % TP : tid / NC, c = LF ? tid / TP : tid % NC;
+      int p, c;   // cell t0 - 2 + c, local y index c + 3
+      item(tid, NC, p, c);
       if (p0 + p < np) {
-        const double mum = s_fm[r][p][c + 1];      // its right face, w.r.t. aR
-        const double mup = s_fm[NR + r][p][c];     // its left face, w.r.t. aL
+        const double mum = s_fm[at(r, p, c + 1, NF)];    // its right face, w.r.t. aR
+        const double mup = s_fm[at(NR + r, p, c, NF)];   // its left face, w.r.t. aL
         double ga[5];
-        ppm_vjp_code(s_code[r][p][c + 1], mup, mum, ga);
+        ppm_vjp_code(s_code[at(r, p, c + 1, NE)], mup, mum, ga);
 #pragma unroll
-        for (int o = 0; o < 5; ++o) s_c[o][p][c] = ga[o];
+        for (int o = 0; o < 5; ++o) s_c[at(o, p, c, NC)] = ga[o];
       }
     }
     __syncthreads();
-    if (tid < TP * TL) {
-      const int p = LF ? tid % TP : tid / TL, t = LF ? tid / TP : tid % TL;
-      if (p0 + p < np && t0 + t < na) {
-        // cell j = t0 + t receives C_o of cell j - (o - 2), local index t + 4 - o
-        double acc = 0.0;
+    if (gown) {
+      // cell j = t0 + t receives C_o of cell j - (o - 2), local index t + 4 - o
+      double sum = 0.0;
 #pragma unroll
-        for (int o = 0; o < 5; ++o) acc += s_c[o][p][t + 4 - o];
-        out[r * N + cell(t0 + t, p)] += acc;
-      }
+      for (int o = 0; o < 5; ++o) sum += s_c[at(o, gpi, gti + 4 - o, NC)];
+      acc[r] += sum;
     }
     __syncthreads();
+  }
+  if (gown) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) out[r * N + gq] = acc[r];
   }
 }
 

@@ -50,6 +50,12 @@ CASES = {
     "c3_3d_order2_kF": lambda: W.config3(n=(12, 10, 8), nsteps=2, precision="fp64"),
     "c4_2d_order1_kF": lambda: W.config4(n=(20, 16), nsteps=3, v_order=1),
     "c2_3d_kE_src": lambda: W.config2(n=(12, 10, 8), nsteps=2),
+    "c1_1d_periodic": lambda: W.config1(n=70, nsteps=3, bc=(0,)),
+    "c4_2d_eddington": lambda: W.config4(n=(20, 16), nsteps=3, closure="eddington"),
+    "c5_3d_eddington": lambda: W.config5(n=(10, 8, 8), nsteps=2, precision="fp64",
+                                         closure="eddington"),
+    # two x tiles (64 + 6 cells) and ragged line blocks along y and z
+    "c5_3d_long_x": lambda: W.config5(n=(70, 9, 6), nsteps=2, precision="fp64"),
 }
 
 
