@@ -285,12 +285,16 @@ __device__ __forceinline__ void source_jac(const DevParams& P, const double* z, 
   }
 }
 
+// Source adjoint, one cell per thread: lam (in: lambda_out, out: lambda_in = mu at
+// the converged state zs), gkP/gkF += tau (dg/dkappa)^T U^T mu, and the optional
+// outputs o1 = a1 mu and o2 = a2 mu + b2 s2.
 template <int ND>
 __global__ void __launch_bounds__(ATHREADS)
 k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
           const double* __restrict__ rho, const double* __restrict__ kP,
           const double* __restrict__ kF, double tau, double* gkP, double* gkF,
-          double* __restrict__ o1, double a1, double* __restrict__ o2, double a2, double b2) {
+          double* __restrict__ o1, double a1, double* __restrict__ o2, double a2,
+          const double* __restrict__ s2, double b2) {
   constexpr int M = 2 + 2 * ND;
   const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
   if (q >= P.N) return;
@@ -305,7 +309,7 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       if (o1) o1[i * N + q] = a1 * mu[i];
-      if (o2) o2[i * N + q] = a2 * mu[i] + (b2 == 0.0 ? 0.0 : b2 * o2[i * N + q]);
+      if (o2) o2[i * N + q] = a2 * mu[i] + (s2 ? b2 * s2[i * N + q] : 0.0);
     }
   };
   const double rq = rho[q], kp = kP[q], kf = P.kF_alias ? kp : kF[q];
@@ -741,14 +745,14 @@ static hipError_t adjoint_nd(const AdjointArgs& A) {
   const unsigned nbc = blocks_for(N);
   const double dt = A.dt;
   for (int n = A.nsteps - 1; n >= 0; --n) {
-    // stage 2 source at y^{n+1}: mu2 in Lc, La = Ln = mu2/2
+    // stage 2 source at y^{n+1}: mu2 in Lc, La = mu2/2
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, Y(n + 1), Lc, A.rho,
-                       A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF, La, 0.5, Ln, 0.5, 0.0);
+                       A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF, La, 0.5, nullptr, 0.0, nullptr, 0.0);
     e = transport_vjp<ND>(P, H(n), Lc, 0.5 * dt, La, s);
     if (e != hipSuccess) return e;
-    // stage 1 source at y^{n+1/2}: mu1 in La, Ln += mu1
+    // stage 1 source at y^{n+1/2}: mu1 in La, Ln = mu1 + mu2/2 (mu2 still in Lc)
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, H(n), La, A.rho, A.kP,
-                       A.kF, dt, A.gkP, A.gkF, nullptr, 0.0, Ln, 1.0, 1.0);
+                       A.kF, dt, A.gkP, A.gkF, nullptr, 0.0, Ln, 1.0, Lc, 0.5);
     e = transport_vjp<ND>(P, Y(n), La, dt, Ln, s);
     if (e != hipSuccess) return e;
     double* t = Lc;
