@@ -185,3 +185,61 @@ def test_patch_energy_gradient_matches_finite_differences(torch_dev, orc):
         Tm[0, j, i] -= hT
         fdT = (J_of(Tp, w.kappa_P) - J_of(Tm, w.kappa_P)) / (2 * hT)
         assert abs(fdT - gT[0, j, i]) <= 1e-5 * abs(gT).max(), (fdT, gT[0, j, i])
+
+
+# ------------------------------------------------ full sizes, a property --
+FULL = {
+    # the 2-D 512^2 adjoint workload (FP64, checkpoints every 20), 40 of its 200 steps
+    "c4_512sq": lambda: W.config4(nsteps=40),
+    # the 3-D 320^3 adjoint grid in FP64, 4 steps with checkpoints every 2 (the adjoint
+    # kernels are the same for the mixed trajectory)
+    "c5_320cubed_fp64": lambda: W.config5(nsteps=4, ckpt_every=2, precision="fp64"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(FULL))
+def test_full_size_gradient_matches_directional_difference(torch_dev, case):
+    """At the full grid sizes and launch shapes of the benchmark's adjoint runs: the
+    gradient (dJ/dT0, dJ/dkappa) of J = sum of E over the central patch, applied to a
+    smooth direction (dT0, dkappa), equals the central difference of J along that
+    direction from the GPU forward step itself (a property that holds at any size)."""
+    torch, dev = torch_dev
+    from paper_2404_08247_amd import autograd as AG, rhd
+    w = FULL[case]()
+    _say("full-size adjoint", case, w.n, w.nsteps, w.ckpt_every)
+    p = w.params
+    nd = w.ndim
+    cv = p["kB_over_mu"] / (p["gamma"] - 1)
+    ke = (w.y0[2 + nd:] ** 2).sum(axis=0) / (2 * w.rho)
+    T0 = _to(torch_dev, (w.y0[1 + nd] - ke) / (w.rho * cv))
+    rho = _to(torch_dev, w.rho)
+    kap = _to(torch_dev, w.kappa_P)
+    mom = _to(torch_dev, w.y0[2 + nd:])
+    mask = _to(torch_dev, w.objective_mask.astype(np.float64))
+    S = rhd.Solver(p, rho, kap, None, w.ckpt_every, dev)
+    J, gk, gT = AG.patch_energy_gradients(p, T0, mom, rho, kap, mask, w.dt, w.nsteps,
+                                          w.ckpt_every, S)
+    kap.requires_grad_(False)
+    # smooth direction: a few low Fourier modes, relative to T0 and kappa
+    shape = w.rho.shape
+    grids = np.meshgrid(*[np.arange(m) * 2 * np.pi / m for m in shape], indexing="ij")
+    phase = sum((j + 1) * g for j, g in enumerate(grids))
+    dT = _to(torch_dev, 0.5 * np.sin(phase + 0.3)) * T0
+    dk = _to(torch_dev, 0.5 * np.cos(2 * phase + 0.1)) * kap
+    F = torch.zeros((nd,) + tuple(T0.shape), dtype=T0.dtype, device=dev)
+    k0 = kap.clone()
+
+    def J_at(h):
+        kap.copy_(k0 + h * dk)   # the handle reads kappa through this tensor
+        T = T0 + h * dT
+        y = AG.initial_state(T, T, F, mom, rho, p)
+        S.step(y, w.dt, w.nsteps)
+        return float((y[0] * mask).sum())
+
+    h = 1e-5
+    fd = (J_at(h) - J_at(-h)) / (2 * h)
+    kap.copy_(k0)
+    terms = (gT * dT).abs().sum().item() + (gk * dk).abs().sum().item()
+    ad = float((gT * dT).sum() + (gk * dk).sum())
+    _say("  directional difference", fd, " adjoint", ad, " rel", abs(fd - ad) / terms)
+    assert abs(fd - ad) <= 1e-6 * terms, (fd, ad, terms)
