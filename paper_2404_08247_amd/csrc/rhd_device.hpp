@@ -145,14 +145,21 @@ __device__ __forceinline__ void closure_dD(int closure, double c, double E, cons
     for (int k = 0; k < ND; ++k) dD[k] = T(0);
     return;
   }
+  // dD depends on F/(cE) only. In float, |F|^2 and (cE)^2 leave the float range
+  // for values of physical size (cE ~ 1e19 and above), so F and cE are first
+  // scaled by the power of two that brings cE into [1/2, 1): exact, and the
+  // same result as unscaled wherever that stays in range.
+  const double cEd = c * E;
+  const double sc = (sizeof(T) < sizeof(double)) ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(cEd))
+                                                  : 1.0;
   T Ft[ND];
   T F2 = T(0);
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
-    Ft[k] = T(F[k]);
+    Ft[k] = T(F[k] * sc);
     F2 += Ft[k] * Ft[k];
   }
-  const T cE = T(c * E);
+  const T cE = T(cEd * sc);
   const T r = rcp(fmax(F2, cE * cE));
   const T f2 = F2 * r;
   const T h = rcp(T(2) + sqrt_1_4(T(4) - T(3) * f2));

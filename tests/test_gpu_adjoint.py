@@ -56,7 +56,13 @@ CASES = {
                                          closure="eddington"),
     # two x tiles (64 + 6 cells) and ragged line blocks along y and z
     "c5_3d_long_x": lambda: W.config5(n=(70, 9, 6), nsteps=2, precision="fp64"),
+    # a mixed-precision handle: the adjoint of the FP64 step along the mixed trajectory
+    # (float32 limiter and closure in the forward), against the oracle's FP64 tangent
+    "c5_3d_mixed": lambda: W.config5(n=(12, 10, 8), nsteps=2),
 }
+# the mixed trajectory differs from the FP64 one by the mixed forward error (<= 1e-7
+# relative per step here), and so does the point at which the step is linearised
+TOL = {"c5_3d_mixed": 1e-6}
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -111,7 +117,7 @@ def test_adjoint_dot_product_matches_oracle_dual(torch_dev, orc, case):
         rhs += float((gF * dkF).sum())
         terms += np.abs(gF * dkF).sum()
     _say("  <lam, J d> =", lhs, " <J^T lam, d> =", rhs, " rel", abs(lhs - rhs) / abs(lhs))
-    assert abs(lhs - rhs) <= 1e-9 * terms, (lhs, rhs, terms)
+    assert abs(lhs - rhs) <= TOL.get(case, 1e-9) * terms, (lhs, rhs, terms)
 
 
 def test_checkpoint_interval_does_not_change_gradients(torch_dev):

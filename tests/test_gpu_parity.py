@@ -96,6 +96,29 @@ def test_transport_matches_oracle(torch_dev, orc, case):
     assert np.all(got[1 + w.ndim:] == 0.0)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_transport_is_scale_free(torch_dev, precision):
+    """The transport is homogeneous of degree one in (E, F): scaling the state by a
+    power of two scales s(y) by the same power, exactly. 2^100 puts E and |F| near
+    1e22, where (cE)^2 and |F|^2 are outside the float range, which the float32
+    closure must not see."""
+    torch, dev = torch_dev
+    w = W.config2(n=(40, 20, 19), precision=precision)
+    _say("transport scale", precision, w.n)
+    y = _rough_state(w, 11)
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, y)
+    s1 = torch.zeros_like(yd)
+    S.transport(yd, s1)
+    lam = 2.0 ** 100
+    s2 = torch.zeros_like(yd)
+    S.transport(yd * lam, s2)
+    a, b = s1.cpu().numpy(), s2.cpu().numpy() / lam
+    assert np.isfinite(b).all()
+    err = _rel_err(b, a, range(1 + w.ndim))
+    assert err.max() == 0.0, err
+
+
 EPS_TRANSPORT_CASES = {
     "1d_reflect_eps": lambda: W.config1(n=300, hll_eps_cells=2.0),
     "2d_periodic_eps": lambda: W.config4(n=(70, 21), hll_eps_cells=1.0),
