@@ -40,54 +40,61 @@ constexpr int ATHREADS = 256;
 // 2 r = -2 l, 3 unchanged). The edges are linear in a0..a4 within a branch, so
 // the code alone fixes their derivatives. Ties go to the earlier case in that
 // order, the same choice as the oracle's dual numbers. Branch-free: the lanes of
-// a wave take different cases.
-__device__ __forceinline__ unsigned slope_case(double dl, double dr, double& s) {
+// a wave take different cases. T is the limiter's arithmetic type: double, or
+// float on differences formed in double (the forward's delta form), which takes
+// the branches the mixed-precision forward step took.
+template <typename T>
+__device__ __forceinline__ unsigned slope_case(T dl, T dr, T& s) {
   // sgn(dc) min(|dc|, 2|dl|, 2|dr|), dc = (dl + dr)/2, compared at half scale
-  const double al = fabs(dl), ar = fabs(dr);
-  const double ac = 0.25 * fabs(dl + dr);
-  const double mlr = fmin(al, ar);
+  const T al = fabs(dl), ar = fabs(dr);
+  const T ac = T(0.25) * fabs(dl + dr);
+  const T mlr = fmin(al, ar);
   const unsigned c = (ac <= mlr) ? 1u : (al <= ar ? 2u : 3u);
-  const bool same = dl * dr > 0.0;   // then sgn(dc) = sgn(dl)
-  s = same ? copysign(2.0 * fmin(ac, mlr), dl) : 0.0;
+  const bool same = dl * dr > T(0);   // then sgn(dc) = sgn(dl)
+  s = same ? copysign(T(2) * fmin(ac, mlr), dl) : T(0);
   return same ? c : 0u;
 }
 
+template <typename T>
 __device__ __forceinline__ unsigned ppm_edges_code(double a0, double a1, double a2, double a3,
                                                    double a4, double& l, double& r) {
-  const double d01 = a1 - a0, d12 = a2 - a1, d23 = a3 - a2, d34 = a4 - a3;
-  double s1, s2, s3;
-  const unsigned c1 = slope_case(d01, d12, s1);
-  const unsigned c2 = slope_case(d12, d23, s2);
-  const unsigned c3 = slope_case(d23, d34, s3);
-  const double lo0 = (-0.5) * d12 - (1.0 / 6.0) * (s2 - s1);
-  const double ro0 = 0.5 * d23 - (1.0 / 6.0) * (s3 - s2);
+  const T d01 = T(a1 - a0), d12 = T(a2 - a1), d23 = T(a3 - a2), d34 = T(a4 - a3);
+  T s1, s2, s3;
+  const unsigned c1 = slope_case<T>(d01, d12, s1);
+  const unsigned c2 = slope_case<T>(d12, d23, s2);
+  const unsigned c3 = slope_case<T>(d23, d34, s3);
+  const T sixth = T(1.0 / 6.0);
+  const T lo0 = T(-0.5) * d12 - sixth * (s2 - s1);
+  const T ro0 = T(0.5) * d23 - sixth * (s3 - s2);
   // CW84 monotonicity: flatten at an extremum, else cap the overshooting side
-  const bool flat = ro0 * lo0 >= 0.0;
-  const double del = ro0 - lo0;
-  const double da = del * (-3.0 * (lo0 + ro0)), dd = del * del;
+  const bool flat = ro0 * lo0 >= T(0);
+  const T del = ro0 - lo0;
+  const T da = del * (T(-3) * (lo0 + ro0)), dd = del * del;
   const bool capl = da > dd, capr = da < -dd;   // never both
   const unsigned cm = flat ? 0u : (capl ? 1u : (capr ? 2u : 3u));
-  const double lo = flat ? 0.0 : (capl ? (-2.0) * ro0 : lo0);
-  const double ro = flat ? 0.0 : (capr ? (-2.0) * lo0 : ro0);
-  l = a2 + lo;
-  r = a2 + ro;
+  const T lo = flat ? T(0) : (capl ? T(-2) * ro0 : lo0);
+  const T ro = flat ? T(0) : (capr ? T(-2) * lo0 : ro0);
+  l = a2 + double(lo);
+  r = a2 + double(ro);
   return c1 | (c2 << 2) | (c3 << 4) | (cm << 6);
 }
 
 // ga[o] = gl dl/da_o + gr dr/da_o in the branch recorded by ppm_edges_code
-__device__ __forceinline__ void ppm_vjp_code(unsigned code, double gl, double gr, double* ga) {
-  auto kl = [](unsigned c) { return c == 1 ? 0.5 : (c == 2 ? 2.0 : 0.0); };
-  auto kr = [](unsigned c) { return c == 1 ? 0.5 : (c == 3 ? 2.0 : 0.0); };
+template <typename T>
+__device__ __forceinline__ void ppm_vjp_code(unsigned code, T gl, T gr, T* ga) {
+  auto kl = [](unsigned c) { return c == 1 ? T(0.5) : (c == 2 ? T(2) : T(0)); };
+  auto kr = [](unsigned c) { return c == 1 ? T(0.5) : (c == 3 ? T(2) : T(0)); };
   const unsigned c1 = code & 3u, c2 = (code >> 2) & 3u, c3 = (code >> 4) & 3u, cm = code >> 6;
-  const double glo = (cm == 3) ? gl : (cm == 2 ? gl - 2.0 * gr : 0.0);
-  const double gro = (cm == 3) ? gr : (cm == 1 ? gr - 2.0 * gl : 0.0);
-  const double gs1 = (1.0 / 6.0) * glo;
-  const double gs2 = (1.0 / 6.0) * (gro - glo);
-  const double gs3 = -(1.0 / 6.0) * gro;
-  const double g01 = kl(c1) * gs1;
-  const double g12 = -0.5 * glo + kr(c1) * gs1 + kl(c2) * gs2;
-  const double g23 = 0.5 * gro + kr(c2) * gs2 + kl(c3) * gs3;
-  const double g34 = kr(c3) * gs3;
+  const T glo = (cm == 3) ? gl : (cm == 2 ? gl - T(2) * gr : T(0));
+  const T gro = (cm == 3) ? gr : (cm == 1 ? gr - T(2) * gl : T(0));
+  const T sixth = T(1.0 / 6.0);
+  const T gs1 = sixth * glo;
+  const T gs2 = sixth * (gro - glo);
+  const T gs3 = -sixth * gro;
+  const T g01 = kl(c1) * gs1;
+  const T g12 = T(-0.5) * glo + kr(c1) * gs1 + kl(c2) * gs2;
+  const T g23 = T(0.5) * gro + kr(c2) * gs2 + kl(c3) * gs3;
+  const T g34 = kr(c3) * gs3;
   ga[0] = -g01;
   ga[1] = g01 - g12;
   ga[2] = g12 - g23 + gl + gr;
@@ -95,57 +102,68 @@ __device__ __forceinline__ void ppm_vjp_code(unsigned code, double gl, double gr
   ga[4] = g34;
 }
 
-// Row DIR of the closure tensor at U = (E, F_1..F_ND) (the forward's formulas)
-// with the partials the HLL adjoint needs, for weights W_k:
-//   Dk[k] = D_DIR,k,   A[j] = sum_k W_k dD_DIR,k/dU_j,   dD[j] = dD_DIR,DIR/dU_j.
-// M1: w = max(|F|^2, (cE)^2), r = 1/w, f2 = |F|^2 r, s = sqrt(4 - 3 f2),
-// h = 1/(2 + s), g = 3 h r F_DIR and D_DIR,k = g F_k + [k = DIR](1/3 - f2 h).
-// Differentiated by hand (exact, the chain rule on these formulas):
-//   df2 = r (d|F|^2 - f2 dw),   dh = h' df2 with h' = 3 h^2/(2 s),
-//   dg = 3 F_DIR (h' r df2 - h r^2 dw) + 3 h r e_DIR,
-//   dD_DIR,k = F_k dg + g e_k - [k = DIR](h + f2 h') df2.
+// Row DIR of the closure tensor at U = (E, F_1..F_ND) with the partials the HLL
+// adjoint needs. The closure depends on F/(cE) only; it is evaluated on the scaled
+// variables e = sc cE and x = sc F in the arithmetic type T; for float, sc is the
+// power of two that brings cE into [1/2, 1) (exact, and in the float range for any
+// units), for double sc = 1:
+//   Dk[k] = D_DIR,k,   A[j] = sum_k W_k dD_DIR,k/dz_j,   dD[j] = dD_DIR,DIR/dz_j,
+// z = (e, x_1..x_ND); d/dE = c sc d/de and d/dF_k = sc d/dx_k. Returns sc.
+// M1 (the forward's formulas): w = max(|x|^2, e^2), r = 1/w, f2 = |x|^2 r,
+// s = sqrt(4 - 3 f2), h = 1/(2 + s), g = 3 h r x_DIR and
+// D_DIR,k = g x_k + [k = DIR](1/3 - f2 h). Differentiated by hand (exact, the chain
+// rule on these formulas):
+//   df2 = r (d|x|^2 - f2 dw),   dh = h' df2 with h' = 3 h^2/(2 s),
+//   dg = 3 x_DIR (h' r df2 - h r^2 dw) + 3 h r e_DIR,
+//   dD_DIR,k = x_k dg + g e_k - [k = DIR](h + f2 h') df2.
 // Eddington: D = I/3, no partials.
-template <int ND, int DIR>
-__device__ __forceinline__ void closure_row_vjp(const DevParams& P, const double* U,
-                                                const double* W, double* Dk, double* A,
-                                                double* dD) {
+template <int ND, int DIR, typename T>
+__device__ __forceinline__ double closure_row_vjp(const DevParams& P, const double* U, const T* W,
+                                                  T* Dk, T* A, T* dD) {
+  const double cEd = P.c * U[0];
+  // (double holds the squares of any physical values: no scaling there)
+  const double sc = (sizeof(T) < sizeof(double)) ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(cEd))
+                                                 : 1.0;
   if (P.closure == 1) {
 #pragma unroll
-    for (int k = 0; k < ND; ++k) Dk[k] = (k == DIR) ? 1.0 / 3.0 : 0.0;
+    for (int k = 0; k < ND; ++k) Dk[k] = (k == DIR) ? T(1.0 / 3.0) : T(0);
 #pragma unroll
-    for (int j = 0; j <= ND; ++j) A[j] = dD[j] = 0.0;
-    return;
+    for (int j = 0; j <= ND; ++j) A[j] = dD[j] = T(0);
+    return sc;
   }
-  double F2 = 0.0, PF = 0.0;
+  const T e = T(cEd * sc);
+  T x[ND];
+  T X2 = T(0), PF = T(0);
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
-    F2 += U[1 + k] * U[1 + k];
-    PF += W[k] * U[1 + k];
+    x[k] = T(U[1 + k] * sc);
+    X2 += x[k] * x[k];
+    PF += W[k] * x[k];
   }
-  const double cE = P.c * U[0];
-  const bool thin = !(F2 < cE * cE);   // the branch max() takes
-  const double r = rcp(thin ? F2 : cE * cE);
-  const double f2 = F2 * r;
-  const double sq = sqrt_1_4(4.0 - 3.0 * f2);
-  const double h = rcp(2.0 + sq);
-  const double FD = U[1 + DIR];
-  const double g = 3.0 * h * r * FD;
-  const double hp = 1.5 * h * h * rcp(sq);
-  const double qp = h + f2 * hp;
-  const double a = 3.0 * FD * hp * r, b = -3.0 * FD * h * r * r;
-  const double wq = W[DIR] * qp;
+  const bool thin = !(X2 < e * e);   // the branch max() takes
+  const T r = rcp(thin ? X2 : e * e);
+  const T f2 = X2 * r;
+  const T sq = sqrt_1_4(T(4) - T(3) * f2);
+  const T h = rcp(T(2) + sq);
+  const T xD = x[DIR];
+  const T g = T(3) * h * r * xD;
+  const T hp = T(1.5) * h * h * rcp(sq);
+  const T qp = h + f2 * hp;
+  const T a = T(3) * xD * hp * r, b = T(-3) * xD * h * r * r;
+  const T wq = W[DIR] * qp;
 #pragma unroll
   for (int j = 0; j <= ND; ++j) {
-    const double dF2 = (j == 0) ? 0.0 : 2.0 * U[j];
-    const double dw = thin ? dF2 : ((j == 0) ? 2.0 * P.c * cE : 0.0);
-    const double df2 = r * (dF2 - f2 * dw);
-    double dg = a * df2 + b * dw;
-    if (j == 1 + DIR) dg += 3.0 * h * r;
-    A[j] = PF * dg - wq * df2 + ((j >= 1) ? g * W[j - 1] : 0.0);
-    dD[j] = FD * dg - qp * df2 + ((j == 1 + DIR) ? g : 0.0);
+    const T dX2 = (j == 0) ? T(0) : T(2) * x[j - 1];
+    const T dw = thin ? dX2 : ((j == 0) ? T(2) * e : T(0));
+    const T df2 = r * (dX2 - f2 * dw);
+    T dg = a * df2 + b * dw;
+    if (j == 1 + DIR) dg += T(3) * h * r;
+    A[j] = PF * dg - wq * df2 + ((j >= 1) ? g * W[j - 1] : T(0));
+    dD[j] = xD * dg - qp * df2 + ((j == 1 + DIR) ? g : T(0));
   }
 #pragma unroll
-  for (int k = 0; k < ND; ++k) Dk[k] = g * U[1 + k] + ((k == DIR) ? (1.0 / 3.0) - f2 * h : 0.0);
+  for (int k = 0; k < ND; ++k) Dk[k] = g * x[k] + ((k == DIR) ? T(1.0 / 3.0) - f2 * h : T(0));
+  return sc;
 }
 
 // The mixed-frame four-force terms per cell, z = (E, F_1..F_ND, E_gas, p_1..p_ND):
@@ -451,46 +469,51 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
 //   Phi_1+k = c chat (E- D-_Dk + E+ D+_Dk)/2 - hS (F+_k - F-_k),
 //   hS = chat sqrt(max(D-_DD, D+_DD))/2,
 // with the closure rows and their partials w.r.t. (E, F) of each side from
-// closure_row_vjp. gm = (dPhi/dU-)^T phi, gp = (dPhi/dU+)^T phi.
-template <int ND, int DIR>
+// closure_row_vjp in the arithmetic type T; states, phi and the results in double.
+// gm = (dPhi/dU-)^T phi, gp = (dPhi/dU+)^T phi.
+template <int ND, int DIR, typename T>
 __device__ __forceinline__ void hll_vjp(const DevParams& P, const double* Um, const double* Up,
                                         const double* phi, double* gm, double* gp) {
   constexpr int NR = 1 + ND;
-  const double* W = phi + 1;   // weights of the flux components
-  double Dm[ND], Dp[ND], Am[NR], Ap[NR], dDm[NR], dDp[NR];
-  closure_row_vjp<ND, DIR>(P, Um, W, Dm, Am, dDm);
-  closure_row_vjp<ND, DIR>(P, Up, W, Dp, Ap, dDp);
+  T W[ND];   // weights of the flux components
+#pragma unroll
+  for (int k = 0; k < ND; ++k) W[k] = T(phi[1 + k]);
+  T Dm[ND], Dp[ND], Am[NR], Ap[NR], dDm[NR], dDp[NR];
+  const double scm = closure_row_vjp<ND, DIR, T>(P, Um, W, Dm, Am, dDm);
+  const double scp = closure_row_vjp<ND, DIR, T>(P, Up, W, Dp, Ap, dDp);
   const bool mside = !(Dm[DIR] < Dp[DIR]);   // the side max() takes
-  const double Dmax = mside ? Dm[DIR] : Dp[DIR];
-  const double sq = sqrt_nonneg(Dmax);
-  const double hS = 0.5 * P.chat * sq;
-  const double dhS = sq > 0.0 ? 0.25 * P.chat * rcp(sq) : 0.0;   // d hS / d D_DD
+  const T sqT = sqrt_nonneg(mside ? Dm[DIR] : Dp[DIR]);
+  const double hS = 0.5 * P.chat * double(sqT);
+  const double dhS = sqT > T(0) ? 0.25 * P.chat * double(rcp(sqT)) : 0.0;   // d hS / d D_DD
   double Sig = 0.0;   // sum_r phi_r (U+_r - U-_r)
 #pragma unroll
   for (int r = 0; r < NR; ++r) Sig += phi[r] * (Up[r] - Um[r]);
-  double WDm = 0.0, WDp = 0.0;
+  T WDm = T(0), WDp = T(0);
 #pragma unroll
   for (int k = 0; k < ND; ++k) {
     WDm += W[k] * Dm[k];
     WDp += W[k] * Dp[k];
   }
+  // E d/dE = e d/de and E d/dF_k = (sc E) d/dx_k on each side
+  const T em = T(P.c * Um[0] * scm), ep = T(P.c * Up[0] * scp);
+  const T Em = T(Um[0] * scm), Ep = T(Up[0] * scp);
   const double hcc = 0.5 * P.c_chat;
   const double sd = Sig * dhS;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     // sum_k phi_1+k d(E D_Dk)/dU_r on each side
-    const double tm = Um[0] * Am[r] + (r == 0 ? WDm : 0.0);
-    const double tp = Up[0] * Ap[r] + (r == 0 ? WDp : 0.0);
-    gm[r] = hcc * tm + hS * phi[r];
-    gp[r] = hcc * tp - hS * phi[r];
+    const T tm = (r == 0) ? em * Am[0] + WDm : Em * Am[r];
+    const T tp = (r == 0) ? ep * Ap[0] + WDp : Ep * Ap[r];
+    gm[r] = hcc * double(tm) + hS * phi[r];
+    gp[r] = hcc * double(tp) - hS * phi[r];
     if (r == 1 + DIR) {
       gm[r] += 0.5 * P.chat_over_c * phi[0];
       gp[r] += 0.5 * P.chat_over_c * phi[0];
     }
     if (mside) {
-      gm[r] -= sd * dDm[r];
+      gm[r] -= sd * double(dDm[r]) * ((r == 0) ? P.c * scm : scm);
     } else {
-      gp[r] -= sd * dDp[r];
+      gp[r] -= sd * double(dDp[r]) * ((r == 0) ? P.c * scp : scp);
     }
   }
 }
@@ -514,7 +537,10 @@ template <> struct TvjpShape<2, 0> { static constexpr int TL = 64, TP = 4; };
 template <> struct TvjpShape<3, 0> { static constexpr int TL = 64, TP = 4; };
 constexpr int TV_NT = 320;
 
-template <int ND, int DIR>
+// TT: arithmetic type of the limiter, closure and the face and stencil adjoints
+// (double; float for a mixed-precision handle, as in its forward step). States,
+// lambda, phi and the outputs stay double.
+template <int ND, int DIR, typename TT>
 __global__ void __launch_bounds__(TV_NT)
 k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam, double scale,
        double* __restrict__ out) {
@@ -533,8 +559,9 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
   //   B: edge states of the cells next to the faces, local y index e + 2 (face
   //      phase), then the PPM contributions (gather);
   // plus the branch codes. A barrier separates every reuse.
-  constexpr int NYB = NR * TP * NYv, NFB = 2 * NR * TP * NF;
-  constexpr int NEB = 2 * NR * TP * NE, NCB = 5 * TP * NC;
+  // (sizes in doubles; the face adjoints and contributions are TT)
+  constexpr int NYB = NR * TP * NYv, NFB = (int)((2 * NR * TP * NF * sizeof(TT) + 7) / 8);
+  constexpr int NEB = 2 * NR * TP * NE, NCB = (int)((5 * TP * NC * sizeof(TT) + 7) / 8);
   __shared__ double s_a[NYB > NFB ? NYB : NFB];
   __shared__ double s_b[NEB > NCB ? NEB : NCB];
   __shared__ unsigned char s_code[NR * TP * NE];
@@ -543,11 +570,11 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
     return LF ? (k * L + t) * TP + p : (k * TP + p) * L + t;
   };
   constexpr int TS = LF ? TP : 1;   // LDS stride between neighbours along the line
-  double* s_y = s_a;                // [NR] x NYv, cells t0-5+t
-  double* s_fm = s_a;               // [2 NR] x NF: mu- (k < NR), mu+ (k >= NR)
-  double* s_eL = s_b;               // [NR] x NE
+  double* s_y = s_a;                           // [NR] x NYv, cells t0-5+t
+  TT* s_fm = reinterpret_cast<TT*>(s_a);       // [2 NR] x NF: mu- (k < NR), mu+ (k >= NR)
+  double* s_eL = s_b;                          // [NR] x NE
   double* s_eR = s_b + NR * TP * NE;
-  double* s_c = s_b;                // [5] x NC
+  TT* s_c = reinterpret_cast<TT*>(s_b);        // [5] x NC
 
   const int tid = threadIdx.x;
   const long long N = P.N;
@@ -621,7 +648,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
         const double* a = &s_y[at(r, p, e, NYv)];
         double l, rr;
         s_code[at(r, p, e, NE)] =
-            (unsigned char)ppm_edges_code(a[0], a[TS], a[2 * TS], a[3 * TS], a[4 * TS], l, rr);
+            (unsigned char)ppm_edges_code<TT>(a[0], a[TS], a[2 * TS], a[3 * TS], a[4 * TS], l, rr);
         s_eL[at(r, p, e, NE)] = l;
         s_eR[at(r, p, e, NE)] = rr;
       }
@@ -643,11 +670,11 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
         Up[r] = s_eL[at(r, p, f + 1, NE)];    // left edge of the cell above it
       }
       double gm[NR], gp[NR];
-      hll_vjp<ND, DIR>(P, Um, Up, phi, gm, gp);
+      hll_vjp<ND, DIR, TT>(P, Um, Up, phi, gm, gp);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        s_fm[at(r, p, f, NF)] = gm[r];
-        s_fm[at(NR + r, p, f, NF)] = gp[r];
+        s_fm[at(r, p, f, NF)] = TT(gm[r]);
+        s_fm[at(NR + r, p, f, NF)] = TT(gp[r]);
       }
     }
   }
@@ -669,10 +696,10 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
       int p, c;   // cell t0 - 2 + c, local y index c + 3
       item(tid, NC, p, c);
       if (p0 + p < np) {
-        const double mum = s_fm[at(r, p, c + 1, NF)];    // its right face, w.r.t. aR
-        const double mup = s_fm[at(NR + r, p, c, NF)];   // its left face, w.r.t. aL
-        double ga[5];
-        ppm_vjp_code(s_code[at(r, p, c + 1, NE)], mup, mum, ga);
+        const TT mum = s_fm[at(r, p, c + 1, NF)];    // its right face, w.r.t. aR
+        const TT mup = s_fm[at(NR + r, p, c, NF)];   // its left face, w.r.t. aL
+        TT ga[5];
+        ppm_vjp_code<TT>(s_code[at(r, p, c + 1, NE)], mup, mum, ga);
 #pragma unroll
         for (int o = 0; o < 5; ++o) s_c[at(o, p, c, NC)] = ga[o];
       }
@@ -680,10 +707,10 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
     __syncthreads();
     if (gown) {
       // cell j = t0 + t receives C_o of cell j - (o - 2), local index t + 4 - o
-      double sum = 0.0;
+      TT sum = TT(0);
 #pragma unroll
       for (int o = 0; o < 5; ++o) sum += s_c[at(o, gpi, gti + 4 - o, NC)];
-      acc[r] += sum;
+      acc[r] += double(sum);
     }
     __syncthreads();
   }
@@ -698,7 +725,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(long long n) { return (unsigned)((n + ATHREADS - 1) / ATHREADS); }
 
-template <int ND, int DIR>
+template <int ND, int DIR, typename TT>
 static void launch_tvjp(const DevParams& P, const double* y, const double* lam, double scale,
                         double* out, hipStream_t s) {
   constexpr int TL = TvjpShape<ND, DIR>::TL, TP = TvjpShape<ND, DIR>::TP;
@@ -706,16 +733,24 @@ static void launch_tvjp(const DevParams& P, const double* y, const double* lam, 
   const int np = (ND >= 2) ? P.n[DIR == 0 ? 1 : 0] : 1;
   const int no = (ND == 3) ? P.n[DIR == 2 ? 1 : 2] : 1;
   const dim3 grid((na + TL - 1) / TL, (np + TP - 1) / TP, no);
-  hipLaunchKernelGGL((k_tvjp<ND, DIR>), grid, dim3(TV_NT), 0, s, P, y, lam, scale, out);
+  hipLaunchKernelGGL((k_tvjp<ND, DIR, TT>), grid, dim3(TV_NT), 0, s, P, y, lam, scale, out);
 }
 
-template <int ND>
-static hipError_t transport_vjp(const DevParams& P, const double* y, const double* lam, double scale,
-                                double* out, hipStream_t s) {
-  launch_tvjp<ND, 0>(P, y, lam, scale, out, s);
-  if constexpr (ND >= 2) launch_tvjp<ND, 1>(P, y, lam, scale, out, s);
-  if constexpr (ND >= 3) launch_tvjp<ND, 2>(P, y, lam, scale, out, s);
+template <int ND, typename TT>
+static hipError_t transport_vjp_t(const DevParams& P, const double* y, const double* lam,
+                                  double scale, double* out, hipStream_t s) {
+  launch_tvjp<ND, 0, TT>(P, y, lam, scale, out, s);
+  if constexpr (ND >= 2) launch_tvjp<ND, 1, TT>(P, y, lam, scale, out, s);
+  if constexpr (ND >= 3) launch_tvjp<ND, 2, TT>(P, y, lam, scale, out, s);
   return hipGetLastError();
+}
+
+// float32 stencil for a mixed-precision handle, double otherwise
+template <int ND>
+static hipError_t transport_vjp(const DevParams& P, bool mixed, const double* y, const double* lam,
+                                double scale, double* out, hipStream_t s) {
+  return mixed ? transport_vjp_t<ND, float>(P, y, lam, scale, out, s)
+               : transport_vjp_t<ND, double>(P, y, lam, scale, out, s);
 }
 
 template <int ND>
@@ -748,12 +783,12 @@ static hipError_t adjoint_nd(const AdjointArgs& A) {
     // stage 2 source at y^{n+1}: mu2 in Lc, La = mu2/2
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, Y(n + 1), Lc, A.rho,
                        A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF, La, 0.5, nullptr, 0.0, nullptr, 0.0);
-    e = transport_vjp<ND>(P, H(n), Lc, 0.5 * dt, La, s);
+    e = transport_vjp<ND>(P, A.mixed, H(n), Lc, 0.5 * dt, La, s);
     if (e != hipSuccess) return e;
     // stage 1 source at y^{n+1/2}: mu1 in La, Ln = mu1 + mu2/2 (mu2 still in Lc)
     hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, H(n), La, A.rho, A.kP,
                        A.kF, dt, A.gkP, A.gkF, nullptr, 0.0, Ln, 1.0, Lc, 0.5);
-    e = transport_vjp<ND>(P, Y(n), La, dt, Ln, s);
+    e = transport_vjp<ND>(P, A.mixed, Y(n), La, dt, Ln, s);
     if (e != hipSuccess) return e;
     double* t = Lc;
     Lc = Ln;
