@@ -138,7 +138,9 @@ rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps);
  *     into g_kappa_P.
  * The forward steps are recomputed from state0 inside the call; each local
  * implicit solve is differentiated with the implicit function theorem at its
- * converged state. Returns RHD_EINVAL (nothing launched) for non-periodic axes,
+ * converged state (in float64). With precision RHD_MIXED the transport adjoint
+ * runs in float32 like the forward's stencil (states, lambda and the results in
+ * float64). Returns RHD_EINVAL (nothing launched) for non-periodic axes,
  * the RK2-SSP scheme, hll_eps_cells > 0 or kappa_T_power != 0, which the adjoint
  * does not cover. */
 rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int32_t nsteps,
