@@ -26,6 +26,8 @@
 //      times mu- of face i+1/2 and mu+ of face i-1/2, giving its contribution
 //      to each of the cells i-2..i+2;
 //   3. per cell j: sum of the contributions addressed to j.
+// On a mixed-precision handle the limiter, closure and stencil adjoints run in
+// float32, as the forward's stencil does; states, lambda and results stay double.
 // Periodic axes only (the library rejects reflecting axes for the adjoint).
 #include "rhd_device.hpp"
 
