@@ -18,6 +18,7 @@
 // flux component negated; below an inflow axis, the fixed inflow state), applied
 // on load.
 #include <climits>
+#include <cmath>
 
 #include "rhd_device.hpp"
 
@@ -34,11 +35,11 @@ constexpr int NTHREADS = 256;
 #ifndef RHD_TX
 #define RHD_TX 32
 #endif
-#ifndef RHD_ZCHUNK
-#define RHD_ZCHUNK 16
+#ifndef RHD_ZCHUNK_MAX
+#define RHD_ZCHUNK_MAX 64
 #endif
-#ifndef RHD_MIN_BLOCKS
-#define RHD_MIN_BLOCKS 1024
+#ifndef RHD_STAGE_SLOTS
+#define RHD_STAGE_SLOTS 512
 #endif
 #ifndef RHD_ZBAL
 #define RHD_ZBAL 1
@@ -605,10 +606,20 @@ static hipError_t launch_nd(const DevParams& P, const double* ys, const double* 
   const int gxn = (nx + TX - 1) / TX, gyn = (ny + TY - 1) / TY;
   int zchunk = nz;
   if (ND == 3) {
-    // enough workgroups to fill 256 CUs several times, chunks of >= 8 planes
+    // Planes per workgroup: long chunks amortise the z-pipeline start and the halo
+    // planes, but the workgroups must still fill the chip. RHD_STAGE_SLOTS of them
+    // run at once (two per CU: the kernel is VGPR-bound). Take the longest chunk of
+    // RHD_ZCHUNK_MAX, half that, ... down to 8 planes whose workgroups fill at least
+    // one such round with the last round at least 95 % full; else 8.
     const long long cols = (long long)gxn * gyn;
-    zchunk = RHD_ZCHUNK;
-    while (zchunk > 8 && cols * ((nz + zchunk - 1) / zchunk) < RHD_MIN_BLOCKS) zchunk /= 2;
+    zchunk = 8;
+    for (int zc = RHD_ZCHUNK_MAX; zc >= 8; zc /= 2) {
+      const double rounds = double(cols * ((nz + zc - 1) / zc)) / RHD_STAGE_SLOTS;
+      if (rounds >= 1.0 && rounds >= 0.95 * std::ceil(rounds)) {
+        zchunk = zc;
+        break;
+      }
+    }
     if (zchunk > nz) zchunk = nz;
   }
   const int gzn = (nz + zchunk - 1) / zchunk;
