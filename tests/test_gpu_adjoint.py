@@ -59,10 +59,11 @@ CASES = {
     # a mixed-precision handle: the adjoint of the FP64 step along the mixed trajectory
     # (float32 limiter and closure in the forward), against the oracle's FP64 tangent
     "c5_3d_mixed": lambda: W.config5(n=(12, 10, 8), nsteps=2),
+    "c5_3d_long_x_mixed": lambda: W.config5(n=(70, 9, 6), nsteps=2),
 }
 # the mixed trajectory differs from the FP64 one by the mixed forward error (<= 1e-7
 # relative per step here), and so does the point at which the step is linearised
-TOL = {"c5_3d_mixed": 1e-6}
+TOL = {"c5_3d_mixed": 1e-6, "c5_3d_long_x_mixed": 1e-6}
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
