@@ -257,8 +257,8 @@ def main():
                          "kernel of known size, to scale the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs (halo exchange over "
-              "xGMI) are a design, not part of this build. Use --gpus 1.", file=sys.stderr)
+        print("bench.py: runs on one GPU only; the multi-GPU path (halo exchange over xGMI) "
+              "is a design, not implemented. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -723,7 +723,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
 }
 
 // ---------------------------------------------------------------------------
-// Host driver of one segment (called by rhd_step_adjoint).
+// Host side of one segment (called by rhd_step_adjoint).
 // ---------------------------------------------------------------------------
 static unsigned blocks_for(long long n) { return (unsigned)((n + ATHREADS - 1) / ATHREADS); }
 
