@@ -60,6 +60,8 @@ CASES = {
     # (float32 limiter and closure in the forward), against the oracle's FP64 tangent
     "c5_3d_mixed": lambda: W.config5(n=(12, 10, 8), nsteps=2),
     "c5_3d_long_x_mixed": lambda: W.config5(n=(70, 9, 6), nsteps=2),
+    # degenerate periodic axes of 2 and 1 cells
+    "c5_3d_thin_axes": lambda: W.config5(n=(10, 2, 1), nsteps=2, precision="fp64"),
 }
 # the mixed trajectory differs from the FP64 one by the mixed forward error (<= 1e-7
 # relative per step here), and so does the point at which the step is linearised

@@ -76,6 +76,10 @@ TRANSPORT_CASES = {
     "3d_periodic_m1": lambda: W.config2(n=(40, 20, 19)),
     "3d_reflect_edd": lambda: W.config2(n=(35, 17, 12), bc=(1, 1, 1), closure="eddington"),
     "3d_mixed_bc_m1": lambda: W.config5(n=(33, 18, 21), bc=(1, 0, 1), precision="fp64"),
+    # degenerate periodic axes of 1 and 2 cells (the stencil wraps onto itself)
+    "3d_thin_axes": lambda: W.config2(n=(20, 2, 1)),
+    "3d_single_x": lambda: W.config2(n=(1, 9, 5)),
+    "2d_single_y": lambda: W.config4(n=(33, 1)),
 }
 
 
@@ -247,6 +251,8 @@ STEP_CASES = {
     "c1_eps_rk2ssp": (lambda: W.config1(nsteps=300, scheme="rk2ssp", hll_eps_cells=1.0), FP64_TOL),
     "c5_small_eps_mixed": (lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="mixed",
                                              hll_eps_cells=2.0), MIXED_TOL),
+    "c2_thin_axes": (lambda: W.config2(n=(20, 2, 1), nsteps=5), FP64_TOL),
+    "c5_single_x_mixed": (lambda: W.config5(n=(1, 9, 5), nsteps=3), MIXED_TOL),
 }
 
 
