@@ -360,6 +360,17 @@ def test_full_size_c2_bench_run_conserves(torch_dev):
 
 
 # ----------------------------------------------------------- properties --
+def test_zero_steps_leave_the_state_untouched(torch_dev):
+    """nsteps = 0 is a valid call: it launches no stage and returns RHD_OK with the
+    state bitwise unchanged."""
+    torch, dev = torch_dev
+    w = W.config2(n=(20, 12, 10), precision="mixed")
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, w.y0)
+    assert S.step(yd, w.dt, 0) == 0
+    assert np.array_equal(yd.cpu().numpy(), w.y0)
+
+
 def test_gpu_steps_are_bitwise_deterministic(torch_dev):
     w = W.config5(n=(36, 20, 18), nsteps=4, precision="fp64")
     outs = []
