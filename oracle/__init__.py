@@ -20,7 +20,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# RHD_ORACLE_LIB names another build of the same source (the planted-mistake
+# test loads deliberately broken copies this way); unset, the in-tree library.
+_LIB_PATH = os.environ.get("RHD_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 OK, ENEWTON, ENONPHYS = 0, 1, 2
 
