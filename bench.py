@@ -1,25 +1,35 @@
 #!/usr/bin/env python3
 """Benchmark of the IMEX PD-ARS radiation step on one MI355X.
 
-Workload (a "step" is one full PD-ARS radiation step: both fused stage kernels,
-transport + local implicit source, over the whole grid): the 3-D 128^3 FP64
-static mixed-regime grid (periodic; log-normal tau_cell in 1e-3..1e3; T = 1 +
-0.1 GRF(8); T_rad offset +/-20 %; chat = c/100), inputs synthetic and resident in
-HBM before the timed region. Prints one JSON line.
+Headline workload (a "step" is one full PD-ARS radiation step: both fused stage
+kernels, transport + local implicit source, over the whole grid): the 3-D 256^3
+dynamic-diffusion grid (periodic; uniform v = 0.01 c along x; 8 x-slabs with
+tau_cell in {0.1, 10, 1000}; Gaussian temperature bump of 16 cells; chat = c/50;
+300 steps), in FP64, with the mixed-precision step on the same inputs beside it.
+Inputs are synthetic and resident in HBM before any timed region. Prints one
+JSON line.
 
-  value     = cells * steps / wall time of the timed rhd_step call (cell-updates/s)
-  roofline  = algorithmic HBM bytes of the dominant stage kernel per launch over its
-              average duration (hipEvents on the library's stream, same timed region)
-  valu      = the same kernel against the FP64 vector peak (78.6 TFLOP/s): FP64
-              FLOPs per launch from the committed rocprofv3 counter summary over
-              the same live duration (null when the kernel sources have changed
-              since the counters were taken, like roofline.traffic)
-  cpu_baseline = the CPU oracle (OpenMP over cells) on a bounded sample of the
-              same workload (rank 0, N = 1)
+Timing protocol
+  warm-up   --warmup steps, then more steps until at least --warmup-seconds of
+            GPU time have passed (steady clocks), on a scratch copy of the state
+  value     cells * K / median over --repeats calls of rhd_step(K steps), each
+            call started from the workload's initial state (reset outside the
+            timed region) and bracketed by one hipEvent pair on the library's
+            stream (the error-word readback at the end of the call included)
+  roofline  algorithmic HBM bytes of the dominant stage kernel per launch over
+            its average duration, from a separate rhd_step_timed call of K steps
+            (per-launch hipEvents on the library's stream; not part of `value`)
+  valu      the same kernel against the FP64 vector peak (78.6 TFLOP/s), with the
+            FP64 FLOPs per launch of the committed rocprofv3 counter summary (null
+            when the kernel sources have changed since the counters were taken,
+            like roofline.traffic)
+  cpu_baseline  the CPU oracle (OpenMP over cells) on the first --cpu-steps steps
+            of the same workload, rate per step extrapolated (rank 0, N = 1)
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -30,7 +40,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
-PROFILE = os.path.join(ROOT, "profiles", "k_stage_c2_128cubed_fp64.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_stage_c3_256cubed_fp64.md")
+HEADLINE = "3-D 256^3 dynamic diffusion, periodic, v = 0.01 c, chat = c/50, 300 steps"
 
 
 def kernel_source_hash():
@@ -70,7 +81,18 @@ def stage_bytes_per_cell(ndim):
     return 8 * (nvar + 2 + nvar), 8 * (2 * nvar + 2 + nvar)
 
 
-def _timed(torch, fn):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _wall(torch, fn):
     torch.cuda.synchronize()
     t = time.perf_counter()
     fn()
@@ -78,32 +100,98 @@ def _timed(torch, fn):
     return time.perf_counter() - t
 
 
-def bench_mixed(torch, rhd, W, dev, to):
-    """3-D 256^3 dynamic-diffusion workload (v = 0.01c, slabs of tau_cell 0.1/10/1000,
-    chat = c/50, 300 steps): FP64 and mixed precision on the same inputs, and the
-    mixed result's L-inf error relative to FP64 per field."""
-    out = {"workload": "3-D 256^3 dynamic diffusion, periodic, chat = c/50, 300 steps"}
-    res = {}
-    for prec in ("fp64", "mixed"):
-        w = W.config3(precision=prec)
-        y = to(w.y0)
-        S = rhd.Solver(w.params, to(w.rho), to(w.kappa_P), None, 0, dev)
-        S.step(y, w.dt, 2)
-        y = to(w.y0)
-        dt_s = _timed(torch, lambda: S.step(y, w.dt, w.nsteps))
-        res[prec] = (y, dt_s)
-        out[prec] = {"value": w.ncells * w.nsteps / dt_s, "unit": "cell-updates/s",
-                     "ms_per_step": dt_s / w.nsteps * 1e3}
-        print(f"[bench] c3 {prec}: {dt_s / w.nsteps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
-    a, b = res["mixed"][0], res["fp64"][0]
-    errs = [float(((a[v] - b[v]).abs().max() / b[v].abs().max()).item()) for v in range(a.shape[0])]
-    out["speedup"] = res["fp64"][1] / res["mixed"][1]
-    out["max_rel_err_vs_fp64_per_field"] = errs
-    return out
+def event_timed(torch, S, y, y0, dt, nsteps, repeats):
+    """`repeats` calls of rhd_step(nsteps) on y, each from y0 (copied in outside
+    the timed region), each timed by one hipEvent pair on the solver's stream and
+    by the host clock around it. Returns (event seconds, wall seconds) lists."""
+    ev_s, wall_s = [], []
+    for _ in range(repeats):
+        y.copy_(y0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(S.stream)
+        S.step(y, dt, nsteps)
+        e1.record(S.stream)
+        torch.cuda.synchronize()
+        wall_s.append(time.perf_counter() - t0)
+        ev_s.append(e0.elapsed_time(e1) * 1e-3)
+    return ev_s, wall_s
+
+
+def warm_up(torch, S, y, y0, dt, nsteps, seconds):
+    """nsteps steps, then batches of steps until `seconds` of wall time have passed."""
+    y.copy_(y0)
+    t0 = time.perf_counter()
+    if nsteps > 0:
+        S.step(y, dt, nsteps)
+    torch.cuda.synchronize()
+    batch = max(1, nsteps)
+    while time.perf_counter() - t0 < seconds:
+        y.copy_(y0)
+        S.step(y, dt, batch)
+        torch.cuda.synchronize()
+
+
+def measure(torch, rhd, w, dev, to, steps, warmup, warmup_s, repeats, label):
+    """Throughput of rhd_step on workload w (the protocol of the module docstring).
+    Returns (line item, solver, state after the last timed call, y0 on device)."""
+    rho, kap = to(w.rho), to(w.kappa_P)
+    y0 = to(w.y0)
+    y = y0.clone()
+    S = rhd.Solver(w.params, rho, kap, None, 0, dev)
+    S._keep = (rho, kap)
+    warm_up(torch, S, y, y0, w.dt, warmup, warmup_s)
+    ev, wall = event_timed(torch, S, y, y0, w.dt, steps, repeats)
+    med = statistics.median(ev)
+    item = {"value": w.ncells * steps / med, "unit": "cell-updates/s",
+            "ms_per_step": med / steps * 1e3, "steps_per_call": steps, "calls": repeats,
+            "call_ms_event": [t * 1e3 for t in ev], "call_ms_wall": [t * 1e3 for t in wall]}
+    print(f"[bench] {label}: {med / steps * 1e3:.4f} ms/step (median of {repeats} calls of "
+          f"{steps} steps; spread {min(ev) / steps * 1e3:.4f}..{max(ev) / steps * 1e3:.4f})",
+          file=sys.stderr, flush=True)
+    return item, S, y, y0
+
+
+def stage_times(S, y, y0, dt, steps):
+    """Average stage-1 / stage-2 kernel durations (s) over a separate call."""
+    y.copy_(y0)
+    ms1, ms2 = S.step_timed(y, dt, steps)
+    return ms1 / steps * 1e-3, ms2 / steps * 1e-3
+
+
+def bench_c1(torch, rhd, W, dev, to, repeats):
+    """1-D 256 cells, reflecting walls, FP64, 1000 steps (launch-latency bound)."""
+    w = W.config1()
+    item, S, _, _ = measure(torch, rhd, w, dev, to, w.nsteps, 50, 0.3, repeats, "c1 fp64")
+    item["us_per_step"] = item["ms_per_step"] * 1e3
+    item["workload"] = "1-D 256 cells, reflecting, FP64, chat = c, 1000 steps"
+    return item
+
+
+def bench_c2(torch, rhd, W, dev, to, repeats):
+    """3-D 128^3 static mixed-regime grid, FP64, 200 steps."""
+    w = W.config2(precision="fp64")
+    item, S, y, y0 = measure(torch, rhd, w, dev, to, w.nsteps, 20, 0.5, repeats, "c2 fp64")
+    t1, t2 = stage_times(S, y, y0, w.dt, w.nsteps)
+    item["stage_us"] = [t1 * 1e6, t2 * 1e6]
+    item["workload"] = "3-D 128^3 static mixed-regime grid, periodic, FP64, chat = c/100, 200 steps"
+    return item
+
+
+def bench_c5_forward(torch, rhd, W, dev, to, repeats):
+    """3-D 320^3 mixed precision, 100 forward steps (no checkpoint copies)."""
+    w = W.config5(precision="mixed")
+    item, S, y, y0 = measure(torch, rhd, w, dev, to, w.nsteps, 5, 0.5, repeats, "c5 mixed forward")
+    item["workload"] = "3-D 320^3 turbulent velocity field, periodic, mixed precision, chat = c/100, 100 steps"
+    del S, y, y0
+    torch.cuda.empty_cache()
+    return item
 
 
 def bench_options(torch, rhd, W, dev, to, nsteps=50):
-    """The same 128^3 FP64 workload with each optional part of the step switched on
+    """The 128^3 FP64 workload with each optional part of the step switched on
     (one at a time), and the Marshak wave (60 cells, 5451 steps at CFL 10): rate
     and time per step, and the ratio to the plain step's time."""
     base = W.config2(precision="fp64")
@@ -132,7 +220,7 @@ def bench_options(torch, rhd, W, dev, to, nsteps=50):
             S.set_radiation_source(jd)
         y = to(base.y0)
         S.step(y, base.dt, 3)
-        dt_s = _timed(torch, lambda: S.step(y, base.dt, nsteps))
+        dt_s = _wall(torch, lambda: S.step(y, base.dt, nsteps))
         if t_plain is None:
             t_plain = dt_s
         out[name] = {"value": base.ncells * nsteps / dt_s, "unit": "cell-updates/s",
@@ -144,7 +232,7 @@ def bench_options(torch, rhd, W, dev, to, nsteps=50):
     y = to(w.y0)
     S.step(y, w.dt, 10)
     y = to(w.y0)
-    dt_s = _timed(torch, lambda: S.step(y, w.dt, w.nsteps))
+    dt_s = _wall(torch, lambda: S.step(y, w.dt, w.nsteps))
     out["marshak_60_cfl10"] = {"steps": w.nsteps, "seconds": dt_s,
                                "us_per_step": dt_s / w.nsteps * 1e6}
     print(f"[bench] marshak: {dt_s:.3f} s for {w.nsteps} steps", file=sys.stderr, flush=True)
@@ -153,9 +241,8 @@ def bench_options(torch, rhd, W, dev, to, nsteps=50):
 
 def bench_hydro(torch, rhd, W, dev, to, nsteps=20):
     """Operator-split radiation hydrodynamics on the 3-D 128^3 workload with a
-    moving gas (rough density, velocities up to 0.5 c_s): hydro steps alone
-    (per-stage kernel time from the trace is in profiles/), and split steps with
-    4 radiation subcycles per hydro step."""
+    moving gas (rough density, velocities up to 0.5 c_s): hydro steps alone, and
+    split steps with 4 radiation subcycles per hydro step."""
     w = W.config2(precision="fp64")
     rng = np.random.default_rng(91)
     p = w.params
@@ -175,11 +262,11 @@ def bench_hydro(torch, rhd, W, dev, to, nsteps=20):
     dt_h = 0.3 * p["dx"] / smax
     nsub = 4
     S.hydro_step(yd, dt_h, 2)
-    t_h = _timed(torch, lambda: S.hydro_step(yd, dt_h, nsteps))
+    t_h = _wall(torch, lambda: S.hydro_step(yd, dt_h, nsteps))
     rd.copy_(to(rho))
     yd.copy_(to(y))
     S.rhd_step(yd, dt_h, nsub, 1)
-    t_s = _timed(torch, lambda: S.rhd_step(yd, dt_h, nsub, nsteps))
+    t_s = _wall(torch, lambda: S.rhd_step(yd, dt_h, nsub, nsteps))
     cells = w.ncells
     print(f"[bench] hydro: {t_h / nsteps * 1e3:.3f} ms/step; split (1 hydro + {nsub} radiation): "
           f"{t_s / nsteps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
@@ -226,7 +313,8 @@ def bench_adjoint(torch, rhd, W, dev, to, config=4):
     print(f"[bench] c{config} adjoint: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms",
           file=sys.stderr, flush=True)
     desc = ("2-D 512^2, FP64, periodic, chat = c, 200 steps, checkpoints every 20" if config == 4 else
-            "3-D 320^3, mixed precision (FP64 adjoint), periodic, chat = c/100, 100 steps, "
+            "3-D 320^3, mixed precision (float32 transport stencil and transport adjoint, FP64 "
+            "source and its transposed-Jacobian solve), periodic, chat = c/100, 100 steps, "
             "checkpoints every 10")
     out = {"workload": desc, "forward_s": fwd, "backward_s": bwd, "adjoint_forward_ratio": bwd / fwd,
            "forward_cell_updates_per_s": w.ncells * w.nsteps / fwd,
@@ -240,18 +328,21 @@ def bench_adjoint(torch, rhd, W, dev, to, config=4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=300,
+                    help="steps per timed rhd_step call (the workload's 300 by default)")
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup-seconds", type=float, default=1.0,
+                    help="minimum warm-up time before the timed calls")
+    ap.add_argument("--repeats", type=int, default=5, help="timed calls (the median is reported)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--cpu-steps", type=int, default=60,
-                    help="oracle steps in the CPU-baseline sample (0 = skip)")
-    ap.add_argument("--cpu-steps-1t", type=int, default=3,
-                    help="oracle steps of the one-thread CPU sample (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=10,
+                    help="oracle steps of the CPU-baseline sample on the headline workload (0 = skip)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the extra line items (same as --extras none)")
-    ap.add_argument("--extras", default="mixed,adjoint,adjoint5,options,hydro",
-                    help="comma list of extra line items: mixed, adjoint (config 4), adjoint5 "
-                         "(config 5), options, hydro, or none")
+    ap.add_argument("--extras", default="mixed,c1,c2,c5,adjoint,adjoint5,options,hydro",
+                    help="comma list of extra line items: mixed (the headline workload in mixed "
+                         "precision), c1, c2, c5 (forward), adjoint (config 4), adjoint5 (config 5), "
+                         "options, hydro, or none")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-mebibyte buffer once (a plain copy "
                          "kernel of known size, to scale the HBM byte counters)")
@@ -260,14 +351,17 @@ def main():
         print("bench.py: runs on one GPU only; the multi-GPU path (halo exchange over xGMI) "
               "is a design, not implemented. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.repeats < 1:
+        print("bench.py: --steps and --repeats must be >= 1", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     from paper_2404_08247_amd import rhd, workloads as W
 
     dev = torch.device("cuda:0")
-    w = W.config2(precision=args.precision)
-    print(f"[bench] workload {w.name} cells={w.ncells} steps={args.steps} warmup={args.warmup}",
-          file=sys.stderr, flush=True)
+    w = W.config3(precision=args.precision)
+    print(f"[bench] workload {w.name} cells={w.ncells} steps={args.steps} warmup={args.warmup} "
+          f"repeats={args.repeats}", file=sys.stderr, flush=True)
 
     def to(a):
         return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -282,20 +376,12 @@ def main():
         print(f"[bench] calibration copy of {nb} bytes done", file=sys.stderr, flush=True)
         del a, b
 
-    rho, kap = to(w.rho), to(w.kappa_P)
-    y = to(w.y0)
-    S = rhd.Solver(w.params, rho, kap, None, 0, dev)
-    if args.warmup > 0:
-        S.step(y, w.dt, args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms1, ms2 = S.step_timed(y, w.dt, args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    head, S, y, y0 = measure(torch, rhd, w, dev, to, args.steps, args.warmup, args.warmup_seconds,
+                             args.repeats, f"c3 {args.precision}")
+    t1, t2 = stage_times(S, y, y0, w.dt, args.steps)
     cells = w.ncells
-    value = cells * args.steps / wall
     b1, b2 = stage_bytes_per_cell(w.ndim)
-    t1, t2 = ms1 / args.steps * 1e-3, ms2 / args.steps * 1e-3
+    tt = "double" if args.precision == "fp64" else "float"
     if t2 >= t1:
         kname, kb, kt = "k_stage<3,STAGE2>", b2, t2
     else:
@@ -303,13 +389,38 @@ def main():
     traffic = measured_per_launch("traffic_bytes_per_launch", kname) if args.precision == "fp64" else None
     flops = measured_per_launch("fp64_flops_per_launch", kname) if args.precision == "fp64" else None
     achieved = kb * cells / kt / 1e9
-    print(f"[bench] stage1 {t1 * 1e6:.1f} us  stage2 {t2 * 1e6:.1f} us  wall/step "
-          f"{wall / args.steps * 1e6:.1f} us", file=sys.stderr, flush=True)
+    print(f"[bench] stage1 {t1 * 1e6:.1f} us  stage2 {t2 * 1e6:.1f} us  (rhd_step_timed, "
+          f"{args.steps} steps)", file=sys.stderr, flush=True)
 
     extras = {}
     want = set() if args.no_extras else set(args.extras.split(","))
     if "mixed" in want:
-        extras["mixed_vs_fp64"] = bench_mixed(torch, rhd, W, dev, to)
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        wm = W.config3(precision=other)
+        item, Sm, ym, _ = measure(torch, rhd, wm, dev, to, args.steps, args.warmup,
+                                  args.warmup_seconds, args.repeats, f"c3 {other}")
+        m1, m2 = stage_times(Sm, ym, to(wm.y0), wm.dt, args.steps)
+        # both states now hold K steps from the same initial state
+        a, b = (ym, y) if other == "mixed" else (y, ym)
+        errs = [float(((a[v] - b[v]).abs().max() / b[v].abs().max()).item()) for v in range(a.shape[0])]
+        item["stage_us"] = [m1 * 1e6, m2 * 1e6]
+        ref = head if other == "mixed" else item
+        mix = item if other == "mixed" else head
+        extras["mixed_vs_fp64"] = {
+            "workload": HEADLINE + " (same inputs, same protocol)", other: item,
+            "speedup_mixed_over_fp64": ref["ms_per_step"] / mix["ms_per_step"],
+            "max_rel_err_vs_fp64_per_field": errs,
+            "error_note": f"L-inf of (mixed - FP64) over max |FP64| per field after {args.steps} steps"}
+        del Sm, ym
+        torch.cuda.empty_cache()
+    if "c1" in want:
+        extras["c1"] = bench_c1(torch, rhd, W, dev, to, args.repeats)
+    if "c2" in want:
+        extras["c2"] = bench_c2(torch, rhd, W, dev, to, args.repeats)
+    del S, y, y0
+    torch.cuda.empty_cache()
+    if "c5" in want:
+        extras["c5_forward"] = bench_c5_forward(torch, rhd, W, dev, to, 3)
     if "adjoint" in want:
         extras["adjoint"] = bench_adjoint(torch, rhd, W, dev, to, 4)
     if "adjoint5" in want:
@@ -322,53 +433,47 @@ def main():
     cpu = None
     if args.cpu_steps > 0:
         import oracle
-        wc = W.config2(precision="fp64")
+        wc = W.config3(precision="fp64")
         tc = time.perf_counter()
         _, st, _ = oracle.step(wc.params, wc.y0, wc.rho, wc.kappa_P, None, wc.dt, args.cpu_steps)
         tcpu = time.perf_counter() - tc
         cpu = {"value": wc.ncells * args.cpu_steps / tcpu, "unit": "cell-updates/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"first {args.cpu_steps} of the 200 steps of the same 128^3 FP64 "
-                         f"workload (OpenMP over cells), {tcpu:.1f} s"}
-        if args.cpu_steps_1t > 0:
-            nt = oracle.num_threads()
-            oracle.set_threads(1)
-            tc = time.perf_counter()
-            oracle.step(wc.params, wc.y0, wc.rho, wc.kappa_P, None, wc.dt, args.cpu_steps_1t)
-            t1c = time.perf_counter() - tc
-            oracle.set_threads(nt)
-            cpu["one_thread"] = {"value": wc.ncells * args.cpu_steps_1t / t1c,
-                                 "unit": "cell-updates/s", "cores": 1,
-                                 "sample": f"first {args.cpu_steps_1t} steps, one thread, "
-                                           f"{t1c:.1f} s"}
+               "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"first {args.cpu_steps} of the 300 steps of the same 256^3 workload in "
+                         f"FP64 (OpenMP over cells), {tcpu:.1f} s; rate per step extrapolated to "
+                         f"the full run"}
+        print(f"[bench] cpu oracle: {args.cpu_steps} steps in {tcpu:.1f} s", file=sys.stderr,
+              flush=True)
 
     line = {
         "metric": "IMEX RHD cell-updates/s, FP64 vs mixed; adjoint/forward time ratio",
-        "value": value,
+        "value": head["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": "3-D 128^3 static mixed-regime grid, periodic, chat = c/100, "
-                               "200 steps", "cells": cells, "precision": args.precision,
-                   "steps_per_call": args.steps},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 "
-                     "FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "config": {"workload": HEADLINE, "cells": cells, "precision": args.precision,
+                   "steps_per_call": args.steps, "timed_calls": args.repeats,
+                   "statistic": "median of hipEvent-timed calls",
+                   "call_ms_event": head["call_ms_event"], "call_ms_wall": head["call_ms_wall"]},
+        "roofline": {"bound": "hbm", "kernel": f"k_stage<3,{kname[-7:-1]},{tt}>",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "algorithmic_bytes_per_launch": kb * cells, "bytes_per_cell": kb,
-                     "avg_launch_us": kt * 1e6},
+                     "avg_launch_us": kt * 1e6, "stage_us": [t1 * 1e6, t2 * 1e6]},
         "valu": None if flops is None else {
             "bound": "alu", "kernel": kname, "fp64_flops_per_launch": flops,
             "achieved": flops / kt / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": flops / kt / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
-            "flops_source": "rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 + _TRANS per dispatch (profiles/)"},
+            "flops_source": "rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 per dispatch (profiles/)"},
         "cpu_baseline": cpu,
     }
     line.update(extras)
