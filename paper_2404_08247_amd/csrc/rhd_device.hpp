@@ -51,7 +51,10 @@ __device__ __forceinline__ float sqrt_1_4(float x) { return __builtin_amdgcn_sqr
 __device__ __forceinline__ double sqrt_nonneg(double x) {
   return x > 0.0 ? sqrt_1_4(x) : 0.0;
 }
-__device__ __forceinline__ float sqrt_nonneg(float x) { return __builtin_amdgcn_sqrtf(x); }
+// float: clamped at zero. In float32 the closure's D_dd across a saturated beam
+// (f = 1, F_d = 0) is 1/3 - f^2 h, which the 1-ulp hardware reciprocal can leave
+// a few ulp below zero.
+__device__ __forceinline__ float sqrt_nonneg(float x) { return __builtin_amdgcn_sqrtf(fmaxf(x, 0.f)); }
 
 // ---------------------------------------------------------------------------
 // PPM (Colella & Woodward 1984), method-of-lines form: limited slopes,
@@ -135,37 +138,69 @@ __device__ __forceinline__ void ppm_edges5(double a0, double a1, double a2, doub
 //   chi = (3 + 4 f^2)/(5 + 2 s) = 1/3 + 2 f^2/(2 + s),
 // and D = (1-chi)/2 I + (3chi-1)/2 n n = I/3 + dD with
 //   dD_jk = -f^2 h delta_jk + 3 h F_j F_k r,   h = 1/(2+s), r = 1/max(|F|^2, (cE)^2).
-// Only dD (small in thick regions) goes through T.
+// Only dD (small in thick regions) goes through T. Ddd is D_DIR,DIR, the
+// component under the square root of the HLL speed.
+//
+// float32: the same tensor written with u = (cE)^2 - |F|^2 (formed in double,
+// so exact enough), b = sqrt((cE)^2 + 3u) = cE s and q = 1/(cE (cE + b) (2cE + b)):
+//   K = 1/(w (2 + s)) = q (cE + b),  dD_jk = K (3 F_j F_k - |F|^2 delta_jk),
+//   D_DIR,DIR = (s - 1)/3 + 3 K F_DIR^2 = u q (2cE + b) + 3 K F_DIR^2,
+// a sum of two non-negative terms; at |F| >= cE (u <= 0, the beam limit f = 1)
+// K = 1/(3|F|^2) and the first term is 0. Across a saturated beam (F_DIR = 0,
+// f = 1) D_DIR,DIR is then exactly 0, where 1/3 + dD_DIR,DIR would leave a
+// rounding residue of a few float ulp, whose square root is a speed error of
+// order 1e-4 chat. One reciprocal and one square root per evaluation.
 // ---------------------------------------------------------------------------
 template <int ND, int DIR, typename T>
 __device__ __forceinline__ void closure_dD(int closure, double c, double E, const double* F,
-                                           T* dD) {
+                                           T* dD, T& Ddd) {
   if (closure == 1) {
 #pragma unroll
     for (int k = 0; k < ND; ++k) dD[k] = T(0);
+    Ddd = T(1.0 / 3.0);
     return;
   }
-  // dD depends on F/(cE) only. In float, |F|^2 and (cE)^2 leave the float range
-  // for values of physical size (cE ~ 1e19 and above), so F and cE are first
-  // scaled by the power of two that brings cE into [1/2, 1): exact, and the
-  // same result as unscaled wherever that stays in range.
   const double cEd = c * E;
-  const double sc = (sizeof(T) < sizeof(double)) ? ldexp(1.0, -__builtin_amdgcn_frexp_exp(cEd))
-                                                  : 1.0;
-  T Ft[ND];
-  T F2 = T(0);
+  if constexpr (sizeof(T) < sizeof(double)) {
+    // dD depends on F/(cE) only. In float, |F|^2 and (cE)^2 leave the float range
+    // for values of physical size (cE ~ 1e19 and above), so F and cE are first
+    // scaled by the power of two that brings cE into [1/2, 1): exact, and the
+    // same result as unscaled wherever that stays in range.
+    const double sc = ldexp(1.0, -__builtin_amdgcn_frexp_exp(cEd));
+    double F2d = 0.0;
+    T Ft[ND];
 #pragma unroll
-  for (int k = 0; k < ND; ++k) {
-    Ft[k] = T(F[k] * sc);
-    F2 += Ft[k] * Ft[k];
+    for (int k = 0; k < ND; ++k) {
+      const double fk = F[k] * sc;
+      Ft[k] = T(fk);
+      F2d += fk * fk;
+    }
+    const double ce = cEd * sc;
+    const T u = T(ce * ce - F2d);
+    const T cE = T(ce), F2 = T(F2d);
+    const bool thin = !(u > T(0));
+    const T b = sqrt_1_4(cE * cE + T(3) * fmax(u, T(0)));
+    const T cpb = cE + b, tpb = cE + cpb;
+    const T q = rcp(thin ? T(3) * F2 : cE * cpb * tpb);
+    const T K = thin ? q : q * cpb;
+    const T iso = thin ? T(0) : u * q * tpb;
+    const T g = T(3) * K * Ft[DIR];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) dD[k] = g * Ft[k] - ((k == DIR) ? F2 * K : T(0));
+    Ddd = iso + g * Ft[DIR];
+  } else {
+    T F2 = T(0);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) F2 += T(F[k]) * T(F[k]);
+    const T cE = T(cEd);
+    const T r = rcp(fmax(F2, cE * cE));
+    const T f2 = F2 * r;
+    const T h = rcp(T(2) + sqrt_1_4(T(4) - T(3) * f2));
+    const T g = T(3) * h * r * T(F[DIR]);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) dD[k] = g * T(F[k]) - ((k == DIR) ? f2 * h : T(0));
+    Ddd = T(1.0 / 3.0) + dD[DIR];
   }
-  const T cE = T(cEd * sc);
-  const T r = rcp(fmax(F2, cE * cE));
-  const T f2 = F2 * r;
-  const T h = rcp(T(2) + sqrt_1_4(T(4) - T(3) * f2));
-  const T g = T(3) * h * r * Ft[DIR];
-#pragma unroll
-  for (int k = 0; k < ND; ++k) dD[k] = g * Ft[k] - ((k == DIR) ? f2 * h : T(0));
 }
 
 // HLL flux along DIR between edge states Um = (E, F..) and Up (RSLA form):
@@ -178,11 +213,10 @@ template <int ND, int DIR, typename T>
 __device__ __forceinline__ void hll_flux(int closure, double c, double chat, double chat_over_c,
                                          double c_chat, const double* Um, const double* Up,
                                          double* fl, double eps_e = 1.0) {
-  T dm[ND], dp[ND];
-  closure_dD<ND, DIR, T>(closure, c, Um[0], Um + 1, dm);
-  closure_dD<ND, DIR, T>(closure, c, Up[0], Up + 1, dp);
-  const T Ddd = T(1.0 / 3.0) + fmax(dm[DIR], dp[DIR]);
-  const double hS = 0.5 * chat * double(sqrt_nonneg(Ddd));
+  T dm[ND], dp[ND], Dm, Dp;
+  closure_dD<ND, DIR, T>(closure, c, Um[0], Um + 1, dm, Dm);
+  closure_dD<ND, DIR, T>(closure, c, Up[0], Up + 1, dp, Dp);
+  const double hS = 0.5 * chat * double(sqrt_nonneg(fmax(Dm, Dp)));
   fl[0] = 0.5 * chat_over_c * (Um[1 + DIR] + Up[1 + DIR]) - eps_e * hS * (Up[0] - Um[0]);
   const T em = T(Um[0]), ep = T(Up[0]);
   const double half_cc = 0.5 * c_chat;
