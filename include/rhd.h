@@ -114,24 +114,30 @@ size_t rhd_workspace_bytes(const rhd_params* p, int32_t adjoint_segment_len);
  *   rho, kappa_P: device float64 [nz][ny][nx]; density and Planck-mean opacity
  *     per unit mass (chi_P = chi_E = rho kappa_P, Sec. 2.1 eq. G0-G1, grey).
  *   kappa_F: flux-mean opacity per unit mass, or NULL (or kappa_P) for kappa_F = kappa_P.
- *   workspace: device memory of ws_bytes >= rhd_workspace_bytes(p, k), 256-byte
- *     aligned; owned by the caller, used exclusively by this handle.
+ *   workspace: device memory of ws_bytes >= rhd_workspace_bytes(p, 0), 256-byte
+ *     aligned; owned by the caller, used exclusively by this handle. The
+ *     adjoint segment length the handle accepts (rhd_step_adjoint's nsteps) is
+ *     the largest k with rhd_workspace_bytes(p, k) <= ws_bytes (0: forward only),
+ *     so a workspace of rhd_workspace_bytes(p, k) bytes allows segments of k steps.
  *   hip_stream: hipStream_t (NULL = default stream) on which all work is enqueued.
- *   adjoint_segment_len: the k the workspace was sized for (0 = forward only).
- * On success *out receives the handle; on failure *out is left untouched. */
+ * On success *out receives the handle; on failure *out is left untouched.
+ * Errors: RHD_EINVAL for invalid parameters or a NULL or misaligned (not 8-byte)
+ * field; RHD_EWORKSPACE for a NULL, not 256-byte aligned or too small workspace. */
 rhd_status rhd_create(const rhd_params* p, const double* rho, const double* kappa_P,
-                      const double* kappa_F, void* workspace, size_t ws_bytes,
-                      int32_t adjoint_segment_len, void* hip_stream, rhd_handle** out);
+                      const double* kappa_F, void* workspace, size_t ws_bytes, void* hip_stream,
+                      rhd_handle** out);
 
 /* Advance state (device float64 [nvar][nz][ny][nx], in/out) by nsteps PD-ARS
- * steps of size dt > 0 (Sec. 3.2-3.3). Two fused stage kernels per step; no host
- * synchronisation until the end of the call. On RHD_ENEWTON / RHD_ENONPHYS the
- * state holds what was computed (every step still ran); rhd_last_error names the
- * smallest failing cell index. */
+ * steps of size dt > 0 (Sec. 3.2-3.3). Two fused stage kernels per step; a 1-D
+ * grid of at most 510 cells without the eps correction runs all nsteps steps in
+ * one single-workgroup launch instead. No host synchronisation until the end of
+ * the call. On RHD_ENEWTON / RHD_ENONPHYS the state holds what was computed
+ * (every step still ran); rhd_last_error names the smallest failing cell index. */
 rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps);
 
-/* Reverse-mode derivative of nsteps steps (nsteps <= the handle's
- * adjoint_segment_len) started from state0 (device, not modified).
+/* Reverse-mode derivative of nsteps steps (1 <= nsteps <= the segment length
+ * that the handle's workspace holds, see rhd_create) started from state0
+ * (device, not modified).
  *   lambda: in: dJ/dy at the end of the segment; out: dJ/dy at its start.
  *   g_kappa_P, g_kappa_F: device [nz][ny][nx]; dJ/dkappa is ADDED (+=). With
  *     kappa_F aliasing kappa_P, g_kappa_F may be NULL and both contributions go
@@ -158,7 +164,9 @@ rhd_status rhd_stage1(rhd_handle* h, const double* y, double* yh, double dt);
 /* rhd_step with per-stage kernel timing: hipEvents are recorded on the handle's
  * stream around every stage launch; on return stage_ms[0] and stage_ms[1] hold
  * the summed durations (ms) of the stage-1 and stage-2 kernels over the nsteps
- * steps (HOST array of 2 doubles). Results are identical to rhd_step. */
+ * steps (HOST array of 2 doubles). Always the two-kernel path (also on the 1-D
+ * grids that rhd_step runs in one launch, where results agree to rounding);
+ * elsewhere results are identical to rhd_step. */
 rhd_status rhd_step_timed(rhd_handle* h, double* state, double dt, int32_t nsteps,
                           double* stage_ms);
 

@@ -120,6 +120,21 @@ Layout layout(const rhd_params* p, int adj_len) {
   return L;
 }
 
+// The longest adjoint segment (steps) whose storage fits in ws_bytes after the
+// forward part of the layout, capped at kMaxSegment; 0 if none fits.
+constexpr int kMaxSegment = 1000000;
+int adjoint_capacity(const rhd_params* p, size_t ws_bytes) {
+  if (layout(p, 1).total > ws_bytes) return 0;
+  // the layout grows by 2 states per step: bisect on the exact size
+  int lo = 1, hi = kMaxSegment;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if (layout(p, mid).total <= ws_bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 rhd::DevParams make_dev(const rhd_params* p, bool alias) {
   rhd::DevParams d{};
   d.ndim = p->ndim;
@@ -187,6 +202,25 @@ rhd_status finish(rhd_handle* h) {
 
 bool misaligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % 8) != 0; }
 
+// nsteps PD-ARS (or RK2-SSP) steps of state on the handle's stream: one
+// single-workgroup launch for a 1-D line that fits one workgroup, else two
+// fused stage kernels per step (y^{n+1/2} in the workspace).
+hipError_t run_steps(rhd_handle* h, double* state, double dt, int nsteps) {
+  const bool mixed = (h->p.precision == RHD_MIXED);
+  if (rhd::line_kernel_applies(h->dp))
+    return rhd::launch_line_steps(h->dp, mixed, state, h->rho, h->kP, h->kF, dt, nsteps, h->err,
+                                  h->stream);
+  for (int n = 0; n < nsteps; ++n) {
+    hipError_t e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, mixed, state, state, h->yhalf,
+                                     h->rho, h->kP, h->kF, dt, h->err, h->stream);
+    if (e != hipSuccess) return e;
+    e = rhd::launch_stage(h->dp, rhd::MODE_STAGE2, mixed, h->yhalf, state, state, h->rho, h->kP,
+                          h->kF, dt, h->err, h->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -197,17 +231,18 @@ size_t rhd_workspace_bytes(const rhd_params* p, int32_t adjoint_segment_len) {
 }
 
 rhd_status rhd_create(const rhd_params* p, const double* rho, const double* kappa_P,
-                      const double* kappa_F, void* workspace, size_t ws_bytes,
-                      int32_t adjoint_segment_len, void* hip_stream, rhd_handle** out) {
+                      const double* kappa_F, void* workspace, size_t ws_bytes, void* hip_stream,
+                      rhd_handle** out) {
   if (!out) return RHD_EINVAL;
   if (!validate(p).empty()) return RHD_EINVAL;
   if (!rho || !kappa_P || misaligned(rho) || misaligned(kappa_P) || misaligned(kappa_F))
     return RHD_EINVAL;
-  if (adjoint_segment_len < 0 || adjoint_segment_len > 1000000) return RHD_EINVAL;
   const bool alias = (kappa_F == nullptr || kappa_F == kappa_P);
-  const Layout L = layout(p, adjoint_segment_len);
-  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < L.total)
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 ||
+      ws_bytes < layout(p, 0).total)
     return RHD_EWORKSPACE;
+  const int adjoint_segment_len = adjoint_capacity(p, ws_bytes);
+  const Layout L = layout(p, adjoint_segment_len);
   rhd_handle* h = new (std::nothrow) rhd_handle();
   if (!h) return RHD_EINVAL;
   h->p = *p;
@@ -239,17 +274,10 @@ rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps) {
   if (!h) return RHD_EINVAL;
   if (!state || misaligned(state) || !std::isfinite(dt) || !(dt > 0.0) || nsteps < 0)
     return set_err(h, RHD_EINVAL, -1, "invalid state pointer, dt or nsteps");
-  const bool mixed = (h->p.precision == RHD_MIXED);
   hipError_t e = rhd::launch_reset_err(h->err, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "reset");
-  for (int n = 0; n < nsteps; ++n) {
-    e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, mixed, state, state, h->yhalf, h->rho, h->kP,
-                          h->kF, dt, h->err, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "stage 1 launch");
-    e = rhd::launch_stage(h->dp, rhd::MODE_STAGE2, mixed, h->yhalf, state, state, h->rho, h->kP,
-                          h->kF, dt, h->err, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "stage 2 launch");
-  }
+  e = run_steps(h, state, dt, nsteps);
+  if (e != hipSuccess) return hip_fail(h, e, "step launch");
   return finish(h);
 }
 
@@ -380,21 +408,14 @@ rhd_status rhd_rhd_step(rhd_handle* h, double* state, double* rho, double dt, in
   if (nsteps < 0 || nsub < 1) return set_err(h, RHD_EINVAL, -1, "need nsteps >= 0 and nsub >= 1");
   rhd_status st = hydro_args(h, state, rho, dt);
   if (st != RHD_OK) return st;
-  const bool mixed = (h->p.precision == RHD_MIXED);
   const double dtr = dt / nsub;
   hipError_t e = rhd::launch_reset_err(h->err, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "reset");
   for (int n = 0; n < nsteps; ++n) {
     e = rhd::launch_hydro_step(h->dp, state, rho, h->yhalf, dt, h->err, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "hydro launch");
-    for (int m = 0; m < nsub; ++m) {
-      e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, mixed, state, state, h->yhalf, h->rho, h->kP,
-                            h->kF, dtr, h->err, h->stream);
-      if (e != hipSuccess) return hip_fail(h, e, "stage 1 launch");
-      e = rhd::launch_stage(h->dp, rhd::MODE_STAGE2, mixed, h->yhalf, state, state, h->rho, h->kP,
-                            h->kF, dtr, h->err, h->stream);
-      if (e != hipSuccess) return hip_fail(h, e, "stage 2 launch");
-    }
+    e = run_steps(h, state, dtr, nsub);
+    if (e != hipSuccess) return hip_fail(h, e, "radiation step launch");
   }
   return finish(h);
 }

@@ -48,6 +48,12 @@ enum BoundaryKind : int { BC_PERIODIC = 0, BC_REFLECT = 1, BC_INFLOW = 2 };
 hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* ysten,
                         const double* yown, double* yout, const double* rho, const double* kP,
                         const double* kF, double dt, unsigned long long* err, hipStream_t s);
+// 1-D grids of at most 510 cells without the eps correction: whole steps in one
+// single-workgroup launch (rhd_forward.hip)
+bool line_kernel_applies(const DevParams& P);
+hipError_t launch_line_steps(const DevParams& P, bool mixed, double* y, const double* rho,
+                             const double* kP, const double* kF, double dt, int nsteps,
+                             unsigned long long* err, hipStream_t s);
 hipError_t launch_source(const DevParams& P, double* y, const double* rho, const double* kP,
                          const double* kF, double tau, unsigned long long* err, hipStream_t s);
 hipError_t launch_reset_err(unsigned long long* err, hipStream_t s);

@@ -67,8 +67,7 @@ def _load():
     pp = ctypes.POINTER(RHDParams)
     L.rhd_workspace_bytes.argtypes = [pp, ctypes.c_int32]
     L.rhd_workspace_bytes.restype = ctypes.c_size_t
-    L.rhd_create.argtypes = [pp, vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_int32, vp,
-                             ctypes.POINTER(vp)]
+    L.rhd_create.argtypes = [pp, vp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.rhd_create.restype = ctypes.c_int
     L.rhd_step.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int32]
     L.rhd_step.restype = ctypes.c_int
@@ -172,7 +171,7 @@ class Solver:
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         st = lib.rhd_create(ctypes.byref(self.rp), _ptr(rho), _ptr(kappa_P), _ptr(kappa_F),
-                            ctypes.c_void_p(self.workspace.data_ptr()), int(nb), self.adj_len,
+                            ctypes.c_void_p(self.workspace.data_ptr()), int(nb),
                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != RHD_OK:
             raise RHDError(st, -1, "rhd_create failed")

@@ -73,18 +73,18 @@ def test_create_rejects_bad_arguments_without_launching():
     fake = ctypes.c_void_p(1 << 20)           # never dereferenced on these paths
     nb = L.rhd_workspace_bytes(ctypes.byref(rp), 0)
     # NULL density
-    assert L.rhd_create(ctypes.byref(rp), None, fake, None, fake, nb, 0, None, ctypes.byref(h)) == -1
+    assert L.rhd_create(ctypes.byref(rp), None, fake, None, fake, nb, None, ctypes.byref(h)) == -1
     # workspace too small / misaligned
-    assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb - 8, 0, None, ctypes.byref(h)) == -5
-    assert L.rhd_create(ctypes.byref(rp), fake, fake, None, ctypes.c_void_p((1 << 20) + 8), nb, 0,
+    assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb - 8, None, ctypes.byref(h)) == -5
+    assert L.rhd_create(ctypes.byref(rp), fake, fake, None, ctypes.c_void_p((1 << 20) + 8), nb,
                         None, ctypes.byref(h)) == -5
     # order 2 with a distinct flux-mean opacity is accepted (3x3 flux solve)
     other = ctypes.c_void_p(1 << 21)
-    assert L.rhd_create(ctypes.byref(rp), fake, fake, other, fake, nb, 0, None, ctypes.byref(h)) == 0
+    assert L.rhd_create(ctypes.byref(rp), fake, fake, other, fake, nb, None, ctypes.byref(h)) == 0
     L.rhd_destroy(h)
     h = ctypes.c_void_p()
     # a valid create binds pointers only (no device work), destroy frees it
-    assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb, 0, None, ctypes.byref(h)) == 0
+    assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb, None, ctypes.byref(h)) == 0
     assert h.value is not None
     # invalid step arguments are rejected before any launch
     assert L.rhd_step(h, None, ctypes.c_double(0.1), 1) == -1
@@ -109,7 +109,7 @@ def test_adjoint_rejects_what_it_does_not_differentiate():
         nb = L.rhd_workspace_bytes(ctypes.byref(rp), 2)
         assert nb > 0
         h = ctypes.c_void_p()
-        assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb, 2, None, ctypes.byref(h)) == 0
+        assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb, None, ctypes.byref(h)) == 0
         st = L.rhd_step_adjoint(h, ctypes.c_void_p(1 << 22), ctypes.c_double(0.1), 1,
                                 ctypes.c_void_p(1 << 23), ctypes.c_void_p(1 << 24), None)
         assert st == -1, bad
@@ -128,7 +128,7 @@ def test_hydro_entry_points_validate_before_launching():
     other = ctypes.c_void_p(1 << 21)
     y = ctypes.c_void_p(1 << 22)
     h = ctypes.c_void_p()
-    assert L.rhd_create(ctypes.byref(rp), rho, other, None, ctypes.c_void_p(1 << 23), nb, 0, None,
+    assert L.rhd_create(ctypes.byref(rp), rho, other, None, ctypes.c_void_p(1 << 23), nb, None,
                         ctypes.byref(h)) == 0
     assert L.rhd_hydro_step(h, y, other, ctypes.c_double(1e-3), 1) == -1
     assert L.rhd_hydro_step(h, y, rho, ctypes.c_double(0.0), 1) == -1
@@ -138,3 +138,24 @@ def test_hydro_entry_points_validate_before_launching():
     assert L.rhd_rhd_step(h, y, other, ctypes.c_double(1e-3), 2, 1) == -1
     assert L.rhd_hydro_signal_speed(h, y, rho, None) == -1
     L.rhd_destroy(h)
+
+
+def test_adjoint_segment_capacity_follows_the_workspace_size():
+    """rhd_create takes no segment length: a workspace of rhd_workspace_bytes(p, k)
+    bytes admits adjoint segments of up to k steps (longer ones are rejected with
+    RHD_EINVAL before any launch), and a forward-only workspace admits none."""
+    from paper_2404_08247_amd import rhd
+    L = rhd.lib
+    fake = ctypes.c_void_p(1 << 20)
+    p = W.config4(n=(16, 12)).params
+    rp = rhd.make_params(p)
+    for k in (0, 1, 2, 5):
+        nb = L.rhd_workspace_bytes(ctypes.byref(rp), k)
+        for slack in (0, 255):
+            h = ctypes.c_void_p()
+            assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb + slack, None,
+                                ctypes.byref(h)) == 0
+            st = L.rhd_step_adjoint(h, ctypes.c_void_p(1 << 22), ctypes.c_double(0.1), k + 1,
+                                    ctypes.c_void_p(1 << 23), ctypes.c_void_p(1 << 24), None)
+            assert st == -1, (k, slack)
+            L.rhd_destroy(h)

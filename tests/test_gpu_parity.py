@@ -150,6 +150,48 @@ def test_transport_with_eps_correction_matches_oracle(torch_dev, orc, case):
     assert np.abs(plain[0] - ref[0]).max() > 1e-6 * np.abs(ref[0]).max()
 
 
+def _beam_state(w, sat=1.0 + 1e-9):
+    """The workload's state with a saturated radiation beam along y: in the
+    columns nx/4 <= x < nx/2, F_y = sat c E and F_x = 0; F = 0 elsewhere. On the
+    x faces inside the beam the M1 closure has f = 1 on both sides, so D_xx = 0
+    and the HLL speed is the square root of zero (sat slightly above 1 keeps the
+    FP64 closure on its clipped branch)."""
+    y = w.y0.copy()
+    nx = y.shape[-1]
+    band = np.zeros(nx, dtype=bool)
+    band[nx // 4: nx // 2] = True
+    y[1] = 0.0
+    y[2] = np.where(band[None, None, :], sat * w.params["c"] * y[0], 0.0)
+    return y
+
+
+def test_saturated_beam_on_mixed_handle(torch_dev, orc):
+    """A beam at f = 1 on a mixed-precision handle: the float32 closure must not
+    produce a negative D_xx under the square root of the HLL speed. Transport and
+    three whole steps stay finite and match the FP64 oracle to the mixed bar."""
+    torch, dev = torch_dev
+    w = W.config4(n=(40, 32), nsteps=3, precision="mixed")
+    _say("saturated beam, mixed", w.n)
+    y = _beam_state(w)
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, y)
+    sd = torch.zeros_like(yd)
+    S.transport(yd, sd)
+    got = sd.cpu().numpy()
+    assert np.isfinite(got).all()
+    ref = orc.transport(w.params, y)
+    err = _rel_err(got, ref, range(1 + w.ndim))
+    assert err.max() < MIXED_TOL, err
+    ref, st, _ = orc.step(w.params, y, w.rho, w.kappa_P, None, w.dt, w.nsteps)
+    assert st == 0
+    S.step(yd, w.dt, w.nsteps)
+    got = yd.cpu().numpy()
+    assert np.isfinite(got).all()
+    err = _rel_err(got, ref, range(w.nvar))
+    _say("  max rel err per field", err)
+    assert err.max() < MIXED_TOL, err
+
+
 # --------------------------------------------------------------- source --
 SOURCE_CASES = {
     "c2_3d": lambda: W.config2(n=(24, 16, 12)),
@@ -357,6 +399,111 @@ def test_full_size_c2_bench_run_conserves(torch_dev):
     pscale = np.abs(y[5:8]).sum() + np.abs(y[1:4]).sum() / (w.params["c"] * w.params["chat"])
     for d in range(3):
         assert abs(t1[1 + d] - t0[1 + d]) < 1e-13 * pscale + 1e-300
+
+
+TOTALS_CASES = {
+    "c1_1d_periodic": lambda: W.config1(n=200, nsteps=20, bc=(0,)),
+    "c4_2d_moving": lambda: W.config4(n=(72, 40), nsteps=10),
+    "c5_3d_turb": lambda: W.config5(n=(36, 20, 18), nsteps=6, precision="fp64"),
+    "c3_3d_mixed": lambda: W.config3(n=(48, 24, 20), nsteps=8, precision="mixed"),
+}
+
+
+def _fsum_totals(p, y, nd):
+    """Sum(E_gas + (c/chat) E) and Sum((rho v)_k + F_k/(c chat)), each an exactly
+    rounded sum (math.fsum) of the per-cell terms, and the sums of their magnitudes."""
+    import math
+    k, ikc = p["c"] / p["chat"], 1.0 / (p["c"] * p["chat"])
+    terms = [np.concatenate([y[1 + nd].ravel(), k * y[0].ravel()])]
+    for d in range(nd):
+        terms.append(np.concatenate([y[2 + nd + d].ravel(), ikc * y[1 + d].ravel()]))
+    return [math.fsum(t) for t in terms], [math.fsum(np.abs(t)) for t in terms]
+
+
+@pytest.mark.parametrize("case", sorted(TOTALS_CASES))
+def test_conserved_totals_match_independent_sums(torch_dev, orc, case):
+    """rhd_conserved_totals (the diagnostics of Sec. 3.3's exact energy and
+    momentum conservation) against exactly rounded host sums of the same state,
+    and against the totals of the oracle's end state: on periodic grids both runs
+    conserve the totals to round-off, so the two end states have the same totals."""
+    w = TOTALS_CASES[case]()
+    nd = w.ndim
+    _say("totals", case, w.n, w.nsteps, w.params["precision"])
+    S = _solver(torch_dev, w)
+    yd = _to(torch_dev, w.y0)
+    got0 = S.conserved_totals(yd)
+    ref0, mag0 = _fsum_totals(w.params, w.y0, nd)
+    for a, b, m in zip(got0, ref0, mag0):
+        assert abs(a - b) <= 1e-14 * m, (a, b, m)
+    S.step(yd, w.dt, w.nsteps)
+    y = yd.cpu().numpy()
+    got = S.conserved_totals(yd)
+    ref, mag = _fsum_totals(w.params, y, nd)
+    for a, b, m in zip(got, ref, mag):
+        assert abs(a - b) <= 1e-14 * m, (a, b, m)
+    yo, st, _ = orc.step(w.params, w.y0, w.rho, w.kappa_P, None, w.dt, w.nsteps)
+    assert st == 0
+    oref, omag = _fsum_totals(w.params, yo, nd)
+    scale = [max(a, b, c) for a, b, c in zip(mag, omag, mag0)]
+    for a, b, m in zip(got, oref, scale):
+        assert abs(a - b) <= 1e-14 * m, (a, b, m)
+    # and both equal the initial totals (conservation on the periodic grid)
+    for a, b, m in zip(got, ref0, scale):
+        assert abs(a - b) <= 1e-14 * m, (a, b, m)
+
+
+LINE_CASES = {
+    "c1_reflect": lambda: W.config1(nsteps=200),
+    "c1_periodic_mixed": lambda: W.config1(n=300, nsteps=50, bc=(0,), precision="mixed"),
+    "c1_rk2ssp_order1": lambda: W.config1(n=128, nsteps=60, scheme="rk2ssp", v_order=1),
+    "marshak_cfl10": lambda: W.marshak(cfl=10.0, t_end=2e-9),
+    "one_cell": lambda: W.config1(n=1, nsteps=20, bc=(0,)),
+    "widest_line": lambda: W.config1(n=510, nsteps=30),
+    "one_past_widest": lambda: W.config1(n=511, nsteps=30),
+}
+
+
+@pytest.mark.parametrize("case", sorted(LINE_CASES))
+def test_single_workgroup_line_steps_match_two_kernel_path(torch_dev, orc, case):
+    """1-D grids of up to 510 cells step in one single-workgroup launch (rhd_step);
+    rhd_step_timed always takes the two-kernel path. Both follow the same
+    arithmetic, so they agree to rounding, and both match the oracle."""
+    torch, dev = torch_dev
+    w = LINE_CASES[case]()
+    _say("line kernel", case, w.n, w.nsteps, w.params.get("precision"))
+    rng = np.random.default_rng(5)
+    y0 = w.y0.copy()
+    if case.startswith("c1"):
+        y0[1] = 0.3 * w.params["c"] * y0[0] * rng.uniform(-1, 1, y0[0].shape)
+    S = _solver(torch_dev, w)
+    a = _to(torch_dev, y0)
+    S.step(a, w.dt, w.nsteps)
+    b = _to(torch_dev, y0)
+    S.step_timed(b, w.dt, w.nsteps)
+    ga, gb = a.cpu().numpy(), b.cpu().numpy()
+    err = _rel_err(ga, gb, range(w.nvar))
+    _say("  line vs two-kernel", err)
+    assert err.max() < 1e-12, err
+    ref, st, _ = orc.step(w.params, y0, w.rho, w.kappa_P, None, w.dt, w.nsteps)
+    assert st == 0
+    err = _rel_err(ga, ref, range(w.nvar))
+    tol = MIXED_TOL if w.params.get("precision") == "mixed" else FP64_TOL
+    assert err.max() < tol, err
+
+
+def test_line_kernel_reports_newton_failure_like_the_two_kernel_path(torch_dev, orc):
+    """An inner Newton cap of 1 fails in every coupled cell: the single-workgroup
+    path reports RHD_ENEWTON with the smallest failing cell, as the oracle does."""
+    from paper_2404_08247_amd import rhd
+    torch, dev = torch_dev
+    w = W.config1(n=64, nsteps=1, newton_maxit=1)
+    _, st, cell = orc.step(w.params, w.y0, w.rho, w.kappa_P, None, w.dt, w.nsteps)
+    assert st != 0
+    S = _solver(torch_dev, w)
+    y = _to(torch_dev, w.y0)
+    got = S.step(y, w.dt, w.nsteps, raise_on_error=False)
+    assert got == rhd.RHD_ENEWTON
+    assert S.last_error()[1] == cell
 
 
 # ----------------------------------------------------------- properties --
