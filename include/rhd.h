@@ -161,6 +161,25 @@ rhd_status rhd_transport(rhd_handle* h, const double* y, double* s);
 rhd_status rhd_source(rhd_handle* h, double* y, double tau);
 rhd_status rhd_stage1(rhd_handle* h, const double* y, double* yh, double dt);
 
+/* rhd_step without a handle or workspace, for callers that cannot allocate
+ * device memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). It allocates nothing: y^{n+1/2} and the error word live in
+ * a static device array of 64 MiB that the library holds on every GPU it runs
+ * on until the process ends. Arguments as for rhd_create and rhd_step (device
+ * pointers; kappa_F NULL for kappa_F = kappa_P; hip_stream NULL = default
+ * stream); fail_cell (HOST, may be NULL) receives the smallest failing cell on
+ * RHD_ENEWTON / RHD_ENONPHYS, else -1. The grid must satisfy
+ * 256 + 8 * nvar * cells <= 64 MiB (about 1.05e6 cells in 3-D, 1.4e6 in 2-D,
+ * 2.1e6 in 1-D); larger grids return RHD_EWORKSPACE before any launch. The
+ * static array is shared by every call on that GPU and keeps the last call's
+ * contents, so calls that overlap on one GPU (other streams or threads) race.
+ * The optional kappa_E and S fields of a handle are not available here.
+ * Returns the statuses of rhd_step (RHD_EINVAL for invalid parameters or
+ * pointers, with nothing launched). */
+rhd_status rhd_step_noalloc(const rhd_params* p, const double* rho, const double* kappa_P,
+                            const double* kappa_F, double* state, double dt, int32_t nsteps,
+                            void* hip_stream, int64_t* fail_cell);
+
 /* rhd_step with per-stage kernel timing: hipEvents are recorded on the handle's
  * stream around every stage launch; on return stage_ms[0] and stage_ms[1] hold
  * the summed durations (ms) of the stage-1 and stage-2 kernels over the nsteps

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -205,19 +206,61 @@ bool misaligned(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) % 8)
 // nsteps PD-ARS (or RK2-SSP) steps of state on the handle's stream: one
 // single-workgroup launch for a 1-D line that fits one workgroup, else two
 // fused stage kernels per step (y^{n+1/2} in the workspace).
-hipError_t run_steps(rhd_handle* h, double* state, double dt, int nsteps) {
-  const bool mixed = (h->p.precision == RHD_MIXED);
-  if (rhd::line_kernel_applies(h->dp))
-    return rhd::launch_line_steps(h->dp, mixed, state, h->rho, h->kP, h->kF, dt, nsteps, h->err,
-                                  h->stream);
+hipError_t run_steps(const rhd::DevParams& dp, bool mixed, double* state, double* yhalf,
+                     const double* rho, const double* kP, const double* kF, double dt, int nsteps,
+                     unsigned long long* err, hipStream_t stream) {
+  if (rhd::line_kernel_applies(dp))
+    return rhd::launch_line_steps(dp, mixed, state, rho, kP, kF, dt, nsteps, err, stream);
   for (int n = 0; n < nsteps; ++n) {
-    hipError_t e = rhd::launch_stage(h->dp, rhd::MODE_STAGE1, mixed, state, state, h->yhalf,
-                                     h->rho, h->kP, h->kF, dt, h->err, h->stream);
+    hipError_t e = rhd::launch_stage(dp, rhd::MODE_STAGE1, mixed, state, state, yhalf, rho, kP,
+                                     kF, dt, err, stream);
     if (e != hipSuccess) return e;
-    e = rhd::launch_stage(h->dp, rhd::MODE_STAGE2, mixed, h->yhalf, state, state, h->rho, h->kP,
-                          h->kF, dt, h->err, h->stream);
+    e = rhd::launch_stage(dp, rhd::MODE_STAGE2, mixed, yhalf, state, state, rho, kP, kF, dt, err,
+                          stream);
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t run_steps(rhd_handle* h, double* state, double dt, int nsteps) {
+  return run_steps(h->dp, h->p.precision == RHD_MIXED, state, h->yhalf, h->rho, h->kP, h->kF, dt,
+                   nsteps, h->err, h->stream);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free step (rhd_step_noalloc): the error word at
+// offset 0 and y^{n+1/2} from offset 256, in a file-scope device array that
+// every GPU the library runs on holds until the process ends. Host code uses
+// its device address from hipGetSymbolAddress (one lookup per device, with that
+// device current), never the array's name.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr size_t kNoallocYhalf = 256;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on the current device (looked up once per device).
+hipError_t noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
   return hipSuccess;
 }
 
@@ -279,6 +322,38 @@ rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps) {
   e = run_steps(h, state, dt, nsteps);
   if (e != hipSuccess) return hip_fail(h, e, "step launch");
   return finish(h);
+}
+
+rhd_status rhd_step_noalloc(const rhd_params* p, const double* rho, const double* kappa_P,
+                            const double* kappa_F, double* state, double dt, int32_t nsteps,
+                            void* hip_stream, int64_t* fail_cell) {
+  if (fail_cell) *fail_cell = -1;
+  if (!validate(p).empty()) return RHD_EINVAL;
+  if (!rho || !kappa_P || !state || misaligned(rho) || misaligned(kappa_P) ||
+      misaligned(kappa_F) || misaligned(state) || !std::isfinite(dt) || !(dt > 0.0) || nsteps < 0)
+    return RHD_EINVAL;
+  // y^{n+1/2} of the two-kernel path must fit the static scratch
+  const size_t need = kNoallocYhalf + (size_t)nvar_of(p) * (size_t)ncells(p) * sizeof(double);
+  if (need > kNoallocScratchBytes) return RHD_EWORKSPACE;
+  const bool alias = (kappa_F == nullptr || kappa_F == kappa_P);
+  const rhd::DevParams dp = make_dev(p, alias);
+  void* base = nullptr;
+  if (noalloc_scratch(&base) != hipSuccess) return RHD_EHIP;
+  auto* err = reinterpret_cast<unsigned long long*>(base);
+  auto* yhalf = reinterpret_cast<double*>(reinterpret_cast<char*>(base) + kNoallocYhalf);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // the error word starts each call from its reset value (a kernel, not a memset)
+  if (rhd::launch_reset_err(err, stream) != hipSuccess) return RHD_EHIP;
+  if (run_steps(dp, p->precision == RHD_MIXED, state, yhalf, rho, kappa_P,
+                alias ? kappa_P : kappa_F, dt, nsteps, err, stream) != hipSuccess)
+    return RHD_EHIP;
+  unsigned long long w[2] = {0, 0};
+  if (hipMemcpyAsync(w, err, sizeof(w), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return RHD_EHIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return RHD_EHIP;
+  if (w[1] == 0) return RHD_OK;
+  if (fail_cell) *fail_cell = (w[0] == ULLONG_MAX) ? -1 : (int64_t)w[0];
+  return (w[1] & rhd::ERR_NEWTON) ? RHD_ENEWTON : RHD_ENONPHYS;
 }
 
 rhd_status rhd_step_timed(rhd_handle* h, double* state, double dt, int32_t nsteps,

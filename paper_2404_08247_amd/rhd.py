@@ -22,7 +22,7 @@ _STATUS = {0: "RHD_OK", -1: "RHD_EINVAL", -2: "RHD_ENEWTON", -3: "RHD_ENONPHYS",
 EXPORTED = ["rhd_workspace_bytes", "rhd_create", "rhd_step", "rhd_step_adjoint", "rhd_transport",
             "rhd_source", "rhd_stage1", "rhd_step_timed", "rhd_conserved_totals", "rhd_last_error",
             "rhd_destroy", "rhd_set_energy_opacity", "rhd_set_radiation_source",
-            "rhd_hydro_step", "rhd_rhd_step", "rhd_hydro_signal_speed"]
+            "rhd_hydro_step", "rhd_rhd_step", "rhd_hydro_signal_speed", "rhd_step_noalloc"]
 
 
 class RHDParams(ctypes.Structure):
@@ -99,6 +99,9 @@ def _load():
     L.rhd_rhd_step.restype = ctypes.c_int
     L.rhd_hydro_signal_speed.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
     L.rhd_hydro_signal_speed.restype = ctypes.c_int
+    L.rhd_step_noalloc.argtypes = [pp, vp, vp, vp, vp, ctypes.c_double, ctypes.c_int32, vp,
+                                   ctypes.POINTER(ctypes.c_int64)]
+    L.rhd_step_noalloc.restype = ctypes.c_int
     return L
 
 
@@ -133,6 +136,19 @@ def make_params(p: dict) -> RHDParams:
     rp.inflow_E = float(p.get("inflow_E", 0.0))
     rp.inflow_F = float(p.get("inflow_F", 0.0))
     return rp
+
+
+def step_noalloc(params: dict, state: torch.Tensor, rho: torch.Tensor, kappa_P: torch.Tensor,
+                 kappa_F: Optional[torch.Tensor], dt: float, nsteps: int,
+                 stream: Optional[torch.cuda.Stream] = None):
+    """rhd_step_noalloc on torch's current stream (or `stream`): returns
+    (status, fail_cell); raises nothing."""
+    s = stream if stream is not None else torch.cuda.current_stream(state.device)
+    cell = ctypes.c_int64(-1)
+    st = lib.rhd_step_noalloc(ctypes.byref(make_params(params)), _ptr(rho), _ptr(kappa_P),
+                              _ptr(kappa_F), _ptr(state), float(dt), int(nsteps),
+                              ctypes.c_void_p(s.cuda_stream), ctypes.byref(cell))
+    return int(st), int(cell.value)
 
 
 def workspace_bytes(p: dict, adjoint_segment_len: int = 0) -> int:

@@ -159,3 +159,26 @@ def test_adjoint_segment_capacity_follows_the_workspace_size():
                                     ctypes.c_void_p(1 << 23), ctypes.c_void_p(1 << 24), None)
             assert st == -1, (k, slack)
             L.rhd_destroy(h)
+
+
+def test_noalloc_step_validates_before_touching_the_gpu():
+    """rhd_step_noalloc rejects invalid parameters, pointers and dt with RHD_EINVAL
+    and a grid whose y^{n+1/2} does not fit its 64 MiB static scratch with
+    RHD_EWORKSPACE, before any HIP call (these calls run on a host without a GPU)."""
+    from paper_2404_08247_amd import rhd
+    L = rhd.lib
+    fake = ctypes.c_void_p(1 << 20)
+    cell = ctypes.c_int64(7)
+    ok = W.config2(n=(16, 12, 10)).params
+    big = W.config2(n=(128, 128, 64)).params        # 8 * 8 * 1048576 B > 64 MiB - 256
+    fits = W.config2(n=(128, 128, 63)).params       # 66060288 + 256 B <= 64 MiB
+    args = lambda p, y, dt: (ctypes.byref(rhd.make_params(p)), fake, fake, None, y,
+                             ctypes.c_double(dt), 1, None, ctypes.byref(cell))
+    assert L.rhd_step_noalloc(*args(dict(ok, chat=2.0), fake, 0.1)) == -1
+    assert cell.value == -1
+    assert L.rhd_step_noalloc(*args(ok, None, 0.1)) == -1
+    assert L.rhd_step_noalloc(*args(ok, ctypes.c_void_p((1 << 20) + 4), 0.1)) == -1
+    assert L.rhd_step_noalloc(*args(ok, fake, -0.1)) == -1
+    assert L.rhd_step_noalloc(*args(big, fake, 0.1)) == -5
+    # a grid that fits gets past the size check (and then needs a GPU)
+    assert L.rhd_step_noalloc(*args(fits, fake, 0.1)) != -5
