@@ -46,10 +46,19 @@ __device__ __forceinline__ double sqrt_1_4(double x) {
   return fma(fma(-s, s, x), h, s);
 }
 __device__ __forceinline__ float sqrt_1_4(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Square root of a normal positive argument to about 2^-46 relative: one
+// Goldschmidt step on the hardware estimate (s = x y, h = y/2, s += s (1/2 - s h)).
+// For the closure and the HLL speed of the transport, whose rounding stays far
+// below the flux differences.
+__device__ __forceinline__ double sqrt_g1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double s = x * y;
+  return fma(s, fma(-s, 0.5 * y, 0.5), s);
+}
 // The same iteration for 0 or a normal positive argument (the HLL signal
 // speed sqrt(D_dd), D_dd in [0, 1]); zero maps to zero.
 __device__ __forceinline__ double sqrt_nonneg(double x) {
-  return x > 0.0 ? sqrt_1_4(x) : 0.0;
+  return x > 0.0 ? sqrt_g1(x) : 0.0;
 }
 // float: clamped at zero. In float32 the closure's D_dd across a saturated beam
 // (f = 1, F_d = 0) is 1/3 - f^2 h, which the 1-ulp hardware reciprocal can leave
@@ -193,9 +202,9 @@ __device__ __forceinline__ void closure_dD(int closure, double c, double E, cons
 #pragma unroll
     for (int k = 0; k < ND; ++k) F2 += T(F[k]) * T(F[k]);
     const T cE = T(cEd);
-    const T r = rcp(fmax(F2, cE * cE));
+    const T r = rcp1(fmax(F2, cE * cE));
     const T f2 = F2 * r;
-    const T h = rcp(T(2) + sqrt_1_4(T(4) - T(3) * f2));
+    const T h = rcp1(T(2) + sqrt_g1(T(4) - T(3) * f2));
     const T g = T(3) * h * r * T(F[DIR]);
 #pragma unroll
     for (int k = 0; k < ND; ++k) dD[k] = g * T(F[k]) - ((k == DIR) ? f2 * h : T(0));
@@ -251,18 +260,25 @@ __device__ __forceinline__ double face_eps(double eps_dx, double chi_a, double c
 // of R changes by <= outer_rtol (relatively, or relative to R).
 // ---------------------------------------------------------------------------
 // (iso, g) of the closure tensor D = iso I + g F F^T (M1: iso = 1/3 - f^2 h,
-// g = 3 h / max(|F|^2, (cE)^2); Eddington: iso = 1/3, g = 0)
+// g = 3 h / max(|F|^2, (cE)^2); Eddington: iso = 1/3, g = 0), evaluated as
+//   u = (cE)^2 - |F|^2, b = sqrt((cE)^2 + 3u) = cE s, q = 1/(cE (cE + b) (2cE + b)),
+//   g = 3 q (cE + b), iso = (s - 1)/3 = u q (2cE + b),
+// and at |F| >= cE (f = 1): g = 1/|F|^2, iso = 0. One square root and one
+// reciprocal (refined once: the closure enters the flux update, whose rounding
+// does not reach the converged result at the tolerance of the iteration).
 __device__ __forceinline__ void closure_ig(int closure, double c, double E, double F2, double& iso,
                                            double& g) {
   iso = 1.0 / 3.0;
   g = 0.0;
   if (closure != 1) {
     const double cE = c * E;
-    const double r = rcp(fmax(F2, cE * cE));
-    const double f2 = F2 * r;
-    const double h = rcp(2.0 + sqrt_1_4(4.0 - 3.0 * f2));
-    g = 3.0 * h * r;
-    iso -= f2 * h;
+    const double u = fma(cE, cE, -F2);
+    const bool thin = !(u > 0.0);
+    const double b = sqrt_1_4(fma(3.0, fmax(u, 0.0), cE * cE));
+    const double cpb = cE + b, tpb = cE + cpb;
+    const double q = rcp1(thin ? 3.0 * F2 : cE * cpb * tpb);
+    g = 3.0 * (thin ? q : q * cpb);
+    iso = thin ? 0.0 : u * q * tpb;
   }
 }
 
@@ -356,6 +372,10 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
   const double ctau = ch * tau;
   // order 1: 1/B = 1/chi_E and the flux denominator do not change between passes
   const double inv_den_o1 = o2 ? 0.0 : rcp(1.0 + ctau * chiF);
+  // The lean source at order 2 has one opacity field (chi_F = chi_E = chi_P, the
+  // same products rho kappa_P): every (chi_F - chi_E) term is exactly zero, and
+  // skipping it leaves the results unchanged bit for bit.
+  const bool dchi_zero = (SV == SRC_LEAN) && o2;
   double Enew = E0;
   unsigned status = 0u;
 
@@ -369,9 +389,15 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     }
     const double KE = 0.5 * rho * v2;
     const double b2 = v2 * P.inv_c2;
-    double iso, g;
-    closure_ig(P.closure, P.c, Eb, F2, iso, g);   // D frozen for this pass
-    const double vDv = iso * v2 + g * vF * vF;
+    // D frozen for this pass. The lean source needs it only in the flux update
+    // after the inner solve (v.D.v enters only (chi_F - chi_E) terms, which are
+    // zero or absent there), so its evaluation overlaps the energy recovery; the
+    // general one needs v.D.v in B before the solve.
+    double iso = 1.0 / 3.0, g = 0.0, vDv = 0.0;
+    if constexpr (GEN) {
+      closure_ig(P.closure, P.c, Eb, F2, iso, g);
+      vDv = iso * v2 + g * vF * vF;
+    }
     // R/(tau chat) = A(T) - B E + C  =>  E(E_gas, R) = (A(T) + C - R/(tau chat)) / B.
     // Order 2: B = chi_E a1 - (chi_F - chi_E)(beta^2 + v.D.v/c^2) with
     // a1 = 1 + beta^2/2, and the flux update divides by a2 = 1 + chat tau chi_F a1.
@@ -427,6 +453,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     //   rhs = F(t) + chat tau [chi_P a T^4 v + chi_F E D v + (chi_F - chi_E) E v],
     // solved by Sherman-Morrison: F = (rhs - b v (v.rhs)/(a + b v^2))/a (eq. numF2
     // when chi_F = chi_E).
+    if constexpr (!GEN) closure_ig(P.closure, P.c, Eb, F2, iso, g);
     Enew = E0 - P.chat_over_c * (Egas - Eg0);
     if constexpr (GEN) Enew += Ssrc;
     const double Tn = (Egas - KE) * inv_Cv;
@@ -444,7 +471,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     }
     const double Tn2 = Tn * Tn;
     const double Bn = ar * Tn2 * Tn2;
-    const double xv = chiP * Bn + (chiF - chiE) * Enew;
+    const double xv = dchi_zero ? chiP * Bn : chiP * Bn + (chiF - chiE) * Enew;
     const double gvF = g * vF;
     double rhs[ND];
     double vr = 0.0;
@@ -466,7 +493,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       const double vn = (P0[k] - (Fn - F0[k]) * P.inv_c_chat) * inv_rho;
       v2n += vn * vn;
       wF_new += vn * Fn;
-      Fv_new += Fb[k] * vn;                               // for v_new . D . v_new
+      if (!dchi_zero) Fv_new += Fb[k] * vn;               // for v_new . D . v_new
       F[k] = Fn;                                          // F_new (output candidate)
       Pm[k] = vn;                                         // v_new (momentum formed below)
     }
@@ -478,10 +505,13 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
       const double b2n = v2n * P.inv_c2;
       const double Tq = (Egas - 0.5 * rho * v2n) * inv_Cv;
       const double Tq2 = Tq * Tq;
-      const double wDw_new = iso * v2n + g * Fv_new * Fv_new;
-      W_old += (chiP * Bn - chiE * Enew) * 0.5 * b2 + (chiF - chiE) * (b2 * Enew + Enew * vDv * P.inv_c2);
-      W_new += (chiP * ar * Tq2 * Tq2 - chiE * Enew) * 0.5 * b2n +
-               (chiF - chiE) * (b2n * Enew + Enew * wDw_new * P.inv_c2);
+      W_old += (chiP * Bn - chiE * Enew) * 0.5 * b2;
+      W_new += (chiP * ar * Tq2 * Tq2 - chiE * Enew) * 0.5 * b2n;
+      if (!dchi_zero) {
+        const double wDw_new = iso * v2n + g * Fv_new * Fv_new;
+        W_old += (chiF - chiE) * (b2 * Enew + Enew * vDv * P.inv_c2);
+        W_new += (chiF - chiE) * (b2n * Enew + Enew * wDw_new * P.inv_c2);
+      }
     }
     W_old *= ctau;
     W_new *= ctau;
