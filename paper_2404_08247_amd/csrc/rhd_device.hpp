@@ -422,14 +422,21 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     const double Aco = chiP0 * ar * (o2 ? 1.0 + 0.5 * b2 : 1.0);
 
     // ---- inner Newton on (E_gas, R) ----
+    // E(E_gas, R) = A' T^4 + C' - R t' with the pass constants A' = Aco/B,
+    // C' = C/B, t' = 1/(tau chat B) and T = E_gas/C_v - KE/C_v; the temperature
+    // of the converged iterate is kept for the energy recovery below.
+    const double AcoB = Aco * inv_B, CcB = Cc * inv_B, itB = inv_tch * inv_B;
+    const double KEc = KE * inv_Cv;
+    const double E0R = GEN ? E0 + Ssrc : E0;
     bool conv = false;
+    double T = 0.0, T2 = 0.0;
     for (int it = 0;; ++it) {
-      const double T = (Egas - KE) * inv_Cv;
-      const double T2 = T * T;
+      T = fma(Egas, inv_Cv, -KEc);
+      T2 = T * T;
       const double gT = tdep ? opacity_tpow(P, T, -1) : 1.0;   // chi(field) / chi(T)
-      const double Er = (Aco * T2 * T2 + Cc - R * inv_tch * gT) * inv_B;
-      const double FG = Egas - Eg0 + k_cc * R;
-      const double FR = Er - E0 - (GEN ? R + Ssrc : R);
+      const double Er = fma(AcoB, T2 * T2, fma(-R * gT, itB, CcB));
+      const double FG = fma(k_cc, R, Egas - Eg0);
+      const double FR = Er - (E0R + R);
       if (fabs(FG) < tol && k_cc * fabs(FR) < tol) {
         conv = true;
         break;
@@ -456,7 +463,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
     if constexpr (!GEN) closure_ig(P.closure, P.c, Eb, F2, iso, g);
     Enew = E0 - P.chat_over_c * (Egas - Eg0);
     if constexpr (GEN) Enew += Ssrc;
-    const double Tn = (Egas - KE) * inv_Cv;
+    const double Tn = T;
     if constexpr (tdep) {   // absorption at the converged T for the flux and the outer test
       const double fT = opacity_tpow(P, Tn, 1);
       chiP = chiP0 * fT;
@@ -469,7 +476,7 @@ __device__ unsigned source_cell(const DevParams& P, double& E, double* F, double
         inv_den = rcp(1.0 + ctau * chiF);
       }
     }
-    const double Tn2 = Tn * Tn;
+    const double Tn2 = T2;
     const double Bn = ar * Tn2 * Tn2;
     const double xv = dchi_zero ? chiP * Bn : chiP * Bn + (chiF - chiE) * Enew;
     const double gvF = g * vF;
