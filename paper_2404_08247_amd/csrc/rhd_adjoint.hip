@@ -319,17 +319,22 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
   const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
   if (q >= P.N) return;
   const long long N = P.N;
-  double z[M], lv[M];
+  // every load is issued here, ahead of the arithmetic, so that the addend s2 and
+  // the accumulated gradients do not wait behind the solve at the end
+  double z[M], lv[M], sv[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     z[j] = zs[j * N + q];
     lv[j] = lam[j * N + q];
+    sv[j] = s2 ? s2[j * N + q] : 0.0;
   }
+  const double gP0 = gkP[q];
+  const double gF0 = gkF ? gkF[q] : 0.0;
   auto outputs = [&](const double* mu) {
 #pragma unroll
     for (int i = 0; i < M; ++i) {
       if (o1) o1[i * N + q] = a1 * mu[i];
-      if (o2) o2[i * N + q] = a2 * mu[i] + (s2 ? b2 * s2[i * N + q] : 0.0);
+      if (o2) o2[i * N + q] = a2 * mu[i] + b2 * sv[i];
     }
   };
   const double rq = rho[q], kp = kP[q], kf = P.kF_alias ? kp : kF[q];
@@ -458,9 +463,13 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
     gk[0] += rq * (aP[i] + kF0 * aF[i] + eP * aE[i]) * um[i];
     gk[1] += rq * aF[i] * um[i];
   }
-  gkP[q] += tau * gk[0];
-  if (gkF) gkF[q] += tau * gk[1];
-  else if (!P.kF_alias) gkP[q] += tau * gk[1];
+  if (gkF) {
+    gkP[q] = gP0 + tau * gk[0];
+    gkF[q] = gF0 + tau * gk[1];
+  } else {
+    const double g = gP0 + tau * gk[0];
+    gkP[q] = P.kF_alias ? g : g + tau * gk[1];
+  }
 #pragma unroll
   for (int i = 0; i < M; ++i) lam[i * N + q] = mu[i];
   outputs(mu);
