@@ -82,14 +82,25 @@ def stage_bytes_per_cell(ndim):
 
 
 def cpu_model():
+    """Model name of the host CPU with its family / model numbers (some virtual
+    machines report only a generic name) and the logical CPUs visible."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    if fields:
+                        break
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                fields.setdefault(k, v)
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    name = fields.get("model name", "unknown")
+    fam, mod = fields.get("cpu family"), fields.get("model")
+    if fam is not None and mod is not None:
+        name += f" (family {fam}, model {mod})"
+    return f"{name}, {os.cpu_count()} logical CPUs visible"
 
 
 def _wall(torch, fn):
