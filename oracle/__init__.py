@@ -6,10 +6,12 @@ plain FP64 implementation of the IMEX PD-ARS radiation step (He, Wibking &
 Krumholz 2024, Sec. 3), shares no code with the HIP path, and is pinned by the
 CPU tests against what the paper and the mathematics fix.
 
-Parity unpinned: the exact PPM/M1 face values in non-smooth mixed-regime fields
-and the M1 closure in semi-transparent regions have no analytic anchor; there
-the oracle is checked only through invariants (conservation, symmetry,
-translation invariance) and limits.
+Where no closed form fixes a value (PPM face states in non-smooth fields), the
+pins are the limiter's defining properties (flattening at an extremum, no
+interior extremum of the parabola, edges within the neighbours' range, order
+kept on monotone data) together with the invariants (conservation, symmetry,
+translation invariance) and limits; the M1 closure is pinned at every flux
+factor by the angular quadrature of its defining intensity.
 """
 from __future__ import annotations
 

@@ -40,6 +40,12 @@ MUTANTS = [
     ("PPM left interface sign", "aL = S(0.5) * (a[1] + ai) - (dm0 - dmm) / S(6.0);",
      "aL = S(0.5) * (a[1] + ai) + (dm0 - dmm) / S(6.0);"),
     ("M1 numerator", "chi = (S(3.0) + S(4.0) * f2) /", "chi = (S(3.0) + S(3.0) * f2) /"),
+    # PPM limiter (CW84) on non-smooth data
+    ("PPM flattening at an extremum dropped", "if ((aR - ai) * (ai - aL) <= S(0.0)) {",
+     "if (false) {"),
+    ("PPM overshoot cap on the wrong edge", "aL = S(3.0) * ai - S(2.0) * aR;",
+     "aR = S(3.0) * ai - S(2.0) * aL;"),
+    ("MC slope kept across an extremum", "if ((ap - a0) * (a0 - am) > S(0.0)) {", "if (true) {"),
     ("divergence sign", "s[(int64_t)r * g.N + c] = s[(int64_t)r * g.N + c] - div;",
      "s[(int64_t)r * g.N + c] = s[(int64_t)r * g.N + c] + div;"),
     # local implicit source (Sec. 3.3)

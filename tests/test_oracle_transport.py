@@ -54,6 +54,44 @@ def test_ppm_monotone_at_a_step(orc):
         assert lo <= aL[i] <= hi and lo <= aR[i] <= hi
 
 
+def test_ppm_limiter_properties_on_rough_data(orc):
+    """The limited parabola of each cell (CW84, as the transport uses it in
+    Sec. 3.3) on rough data, where no polynomial identity applies. What the
+    limiter is for fixes these properties: a cell whose average is a strict
+    local extremum is flattened to its average; every other cell is flat or
+    carries a parabola without an interior extremum (|a6| <= |aR - aL| with
+    a6 = 6 a - 3 (aL + aR)); both edges stay within the range of the cell and
+    its two neighbours; on increasing data the edges keep the order
+    a[i-1] <= aL <= a[i] <= aR <= a[i+1]."""
+    rng = np.random.default_rng(11)
+    eps = np.finfo(float).eps
+    n = 40
+    for trial in range(160):
+        kind = trial % 4
+        if kind == 0:
+            a = rng.normal(size=n)                                   # noise
+        elif kind == 1:
+            a = np.cumsum(rng.exponential(size=n))                   # increasing, rough
+        elif kind == 2:
+            a = np.where(rng.random(n) < 0.2, 5.0, 0.0) + 1e-3 * rng.normal(size=n)  # spikes
+        else:
+            a = np.round(3.0 * rng.normal(size=n)) / 3.0             # plateaus and steps
+        aL, aR = orc.ppm_edges(a)
+        for i in range(2, n - 2):
+            ai, l, r = a[i], aL[i], aR[i]
+            lo, hi = min(a[i - 1], ai, a[i + 1]), max(a[i - 1], ai, a[i + 1])
+            assert lo <= l <= hi and lo <= r <= hi, (trial, i)
+            flat = (l == ai and r == ai)
+            if (ai > a[i - 1] and ai > a[i + 1]) or (ai < a[i - 1] and ai < a[i + 1]):
+                assert flat, (trial, i)
+            if not flat:
+                a6 = 6.0 * ai - 3.0 * (l + r)
+                tol = 8 * eps * (6 * abs(ai) + 3 * abs(l) + 3 * abs(r))
+                assert abs(a6) <= abs(r - l) + tol, (trial, i, a6, r - l)
+            if kind == 1:
+                assert a[i - 1] <= l <= ai <= r <= a[i + 1], (trial, i)
+
+
 # ------------------------------------------------------------------ closure --
 def _m1_by_quadrature(f_target):
     """Eddington factor of the intensity I(mu) ~ (1 - b mu)^-4 (an isotropic
