@@ -37,6 +37,8 @@ MUTANTS = [
     # transport arithmetic
     ("HLL dissipation sign", "- S(0.5) * (q == 0 ? eps : S(1.0)) * smax_ * (Up[q] - Um[q]);",
      "+ S(0.5) * (q == 0 ? eps : S(1.0)) * smax_ * (Up[q] - Um[q]);"),
+    ("eps applied to the F rows too", "- S(0.5) * (q == 0 ? eps : S(1.0)) * smax_",
+     "- S(0.5) * eps * smax_"),
     ("PPM left interface sign", "aL = S(0.5) * (a[1] + ai) - (dm0 - dmm) / S(6.0);",
      "aL = S(0.5) * (a[1] + ai) + (dm0 - dmm) / S(6.0);"),
     ("M1 numerator", "chi = (S(3.0) + S(4.0) * f2) /", "chi = (S(3.0) + S(3.0) * f2) /"),

@@ -247,6 +247,19 @@ def test_eps_correction_scales_only_the_energy_dissipation(orc):
     assert np.array_equal(a[1:], b[1:])
     assert orc.face_eps(p, 3.0 / p["dx"], 3.0 / p["dx"]) == 1.0 / 6.0
     assert orc.face_eps(w.params, 1e9, 1e9) == 1.0   # correction off
+    # With F != 0 the F rows still carry their full dissipation (bitwise the plain
+    # HLL rows), and the energy row is affine in eps: s_E(eps) - s_E(1) =
+    # (eps - 1) times the energy dissipation, the same for two values of eps.
+    rng = np.random.default_rng(5)
+    y[1:4] = 0.3 * rng.uniform(-1.0, 1.0, y[1:4].shape) * w.params["c"] * y[0]
+    a = orc.transport(w.params, y)
+    diss = []
+    for t in (7.5, 30.0):
+        kap_t = np.full_like(w.kappa_P, t / (2.0 * w.params["dx"] * w.rho))
+        b = orc.transport(p, y, w.rho, kap_t)
+        assert np.array_equal(a[1:], b[1:])
+        diss.append((b[0] - a[0]) / (1.0 / t - 1.0))
+    np.testing.assert_allclose(diss[1], diss[0], rtol=0, atol=1e-12 * np.abs(diss[0]).max())
 
 
 def test_eps_correction_targets_the_hll_diffusion_not_the_rk2ssp_mode(orc):
