@@ -66,6 +66,44 @@ MUTANTS = [
     ("flux update drops the Doppler term D v",
      "bx[i] = F0[i] + ch * tau * (chiP * Bn * v[i] + chiF * Enew * Dv[i] + (chiF - chiE) * Enew * v[i]);",
      "bx[i] = F0[i] + ch * tau * (chiP * Bn * v[i] + (chiF - chiE) * Enew * v[i]);"),
+    # c / chat mix-ups (Sec. 3.1: the reduced speed enters the transport and the
+    # R / (tau chat) exchange, the true c the v/c terms and the closure)
+    ("beta^2 over c chat", "const S beta2 = v2 / (c * c);", "const S beta2 = v2 / (c * ch);"),
+    ("v.F term over c chat", "Cc = (S(2.0) * chiE - chiF) * vF / (c * c);",
+     "Cc = (S(2.0) * chiE - chiF) * vF / (c * ch);"),
+    ("R over tau c", "S Er = (A + Cc - R / (tau * ch)) / B;", "S Er = (A + Cc - R / (tau * c)) / B;"),
+    ("order-1 flux denominator with c", "Fnew[k] = num / (S(1.0) + ch * chiF * tau);",
+     "Fnew[k] = num / (S(1.0) + c * chiF * tau);"),
+    ("momentum over c^2", "Pnew[k] = P0[k] - (Fnew[k] - F0[k]) / (c * ch);",
+     "Pnew[k] = P0[k] - (Fnew[k] - F0[k]) / (c * c);"),
+    ("flux rows with c^2", "phim[1 + k] = c * ch * Um[0] * Dm[d][k];",
+     "phim[1 + k] = c * c * Um[0] * Dm[d][k];"),
+    # stage coefficients of PD-ARS (Sec. 3.2)
+    ("stage-2 source over dt", "p->scheme == 0 ? 0.5 * dt : dt, status", "p->scheme == 0 ? dt : dt, status"),
+    ("stage-2 transport over dt", "if (r < nr) comb = comb + S(0.5 * dt) * s[q];",
+     "if (r < nr) comb = comb + S(dt) * s[q];"),
+    ("stage 2 without the average of y^n", "S comb = S(0.5) * (y[q] + yh[q]);", "S comb = yh[q];"),
+    ("stage-1 source over dt/2", "apply_source(p, g, yh.data(), rho, kP, kF, kE, jS, dt, status",
+     "apply_source(p, g, yh.data(), rho, kP, kF, kE, jS, 0.5 * dt, status"),
+    # order-2 terms and the gas temperature
+    ("emission without its order-2 factor", "S A = chiP * ar * (T2 * T2) * Afac;",
+     "S A = chiP * ar * (T2 * T2);"),
+    ("order-2 B: v.D.v sign",
+     "B = chiE * (S(1.0) + S(0.5) * beta2) - (chiF - chiE) * (beta2 + vDv / (c * c));",
+     "B = chiE * (S(1.0) + S(0.5) * beta2) - (chiF - chiE) * (beta2 - vDv / (c * c));"),
+    ("order-2 flux matrix without beta^2",
+     "const S a = S(1.0) + ch * chiF * (S(1.0) + S(0.5) * beta2) * tau;",
+     "const S a = S(1.0) + ch * chiF * tau;"),
+    ("order-2 flux matrix: (chi_F - chi_E) term sign",
+     "const S bfac = ch * tau * (chiF - chiE) * S(2.0) / (c * c);",
+     "const S bfac = -ch * tau * (chiF - chiE) * S(2.0) / (c * c);"),
+    ("kinetic energy dropped from T", "S T = (Egas - KE) / Cv;", "S T = Egas / Cv;"),
+    ("kinetic energy dropped from the converged T", "const S Tn = (Egas - KE) / Cv;",
+     "const S Tn = Egas / Cv;"),
+    # transport pieces
+    ("HLL speed without its square root", "S smax_ = ch * ssqrt(smax(Dm[d][d], Dp[d][d]));",
+     "S smax_ = ch * smax(Dm[d][d], Dp[d][d]);"),
+    ("closure isotropic part sign", "S a = S(0.5) * (S(1.0) - chi);", "S a = S(0.5) * (S(1.0) + chi);"),
 ]
 
 
