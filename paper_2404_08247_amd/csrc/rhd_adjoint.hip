@@ -305,36 +305,38 @@ __device__ __forceinline__ void source_jac(const DevParams& P, const double* z, 
   }
 }
 
-// Source adjoint, one cell per thread: lam (in: lambda_out, out: lambda_in = mu at
-// the converged state zs), gkP/gkF += tau (dg/dkappa)^T U^T mu, and the optional
-// outputs o1 = a1 mu and o2 = a2 mu + b2 s2.
+// Source adjoint, one cell per thread, at the converged state zs:
+//   lambda = ls lsrc + [tin; 0]   (tin: the first 1 + ND rows, or null),
+//   mu = A^{-T} lambda into mout,  gkP/gkF += tau (dg/dkappa)^T U^T mu,
+//   and optionally o2 = mu + b2 lsrc.
+// mout may be lsrc or tin (each cell is read in full before it is written).
 template <int ND>
 __global__ void __launch_bounds__(ATHREADS)
-k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
-          const double* __restrict__ rho, const double* __restrict__ kP,
-          const double* __restrict__ kF, double tau, double* gkP, double* gkF,
-          double* __restrict__ o1, double a1, double* __restrict__ o2, double a2,
-          const double* __restrict__ s2, double b2) {
+k_src_adj(DevParams P, const double* __restrict__ zs, const double* lsrc, double ls,
+          const double* tin, double* mout, const double* __restrict__ rho,
+          const double* __restrict__ kP, const double* __restrict__ kF, double tau, double* gkP,
+          double* gkF, double* __restrict__ o2, double b2) {
   constexpr int M = 2 + 2 * ND;
+  constexpr int NRr = 1 + ND;
   const long long q = (long long)blockIdx.x * ATHREADS + threadIdx.x;
   if (q >= P.N) return;
   const long long N = P.N;
-  // every load is issued here, ahead of the arithmetic, so that the addend s2 and
-  // the accumulated gradients do not wait behind the solve at the end
+  // every load is issued here, ahead of the arithmetic, so that the addend of o2
+  // and the accumulated gradients do not wait behind the solve at the end
   double z[M], lv[M], sv[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     z[j] = zs[j * N + q];
-    lv[j] = lam[j * N + q];
-    sv[j] = s2 ? s2[j * N + q] : 0.0;
+    sv[j] = lsrc[j * N + q];
+    lv[j] = ls * sv[j] + ((tin && j < NRr) ? tin[j * N + q] : 0.0);
   }
   const double gP0 = gkP[q];
   const double gF0 = gkF ? gkF[q] : 0.0;
   auto outputs = [&](const double* mu) {
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-      if (o1) o1[i * N + q] = a1 * mu[i];
-      if (o2) o2[i * N + q] = a2 * mu[i] + b2 * sv[i];
+      mout[i * N + q] = mu[i];
+      if (o2) o2[i * N + q] = mu[i] + b2 * sv[i];
     }
   };
   const double rq = rho[q], kp = kP[q], kf = P.kF_alias ? kp : kF[q];
@@ -470,8 +472,6 @@ k_src_adj(DevParams P, const double* __restrict__ zs, double* __restrict__ lam,
     const double g = gP0 + tau * gk[0];
     gkP[q] = P.kF_alias ? g : g + tau * gk[1];
   }
-#pragma unroll
-  for (int i = 0; i < M; ++i) lam[i * N + q] = mu[i];
   outputs(mu);
 }
 
@@ -554,7 +554,7 @@ constexpr int TV_NT = 320;
 template <int ND, int DIR, typename TT>
 __global__ void __launch_bounds__(TV_NT)
 k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam, double scale,
-       double* __restrict__ out) {
+       double* __restrict__ out, int accumulate) {
   constexpr int NR = 1 + ND;
   constexpr int TL = TvjpShape<ND, DIR>::TL, TP = TvjpShape<ND, DIR>::TP;
   constexpr int NYv = TL + 10, NF = TL + 5, NC = TL + 4, NE = TL + 6;
@@ -700,7 +700,7 @@ k_tvjp(DevParams P, const double* __restrict__ y, const double* __restrict__ lam
   const long long gq = gown ? cell(t0 + gti, gpi) : 0;
   double acc[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) acc[r] = gown ? out[r * N + gq] : 0.0;
+  for (int r = 0; r < NR; ++r) acc[r] = (gown && accumulate) ? out[r * N + gq] : 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (tid < TP * NC) {
@@ -738,30 +738,33 @@ static unsigned blocks_for(long long n) { return (unsigned)((n + ATHREADS - 1) /
 
 template <int ND, int DIR, typename TT>
 static void launch_tvjp(const DevParams& P, const double* y, const double* lam, double scale,
-                        double* out, hipStream_t s) {
+                        double* out, bool accumulate, hipStream_t s) {
   constexpr int TL = TvjpShape<ND, DIR>::TL, TP = TvjpShape<ND, DIR>::TP;
   const int na = P.n[DIR];
   const int np = (ND >= 2) ? P.n[DIR == 0 ? 1 : 0] : 1;
   const int no = (ND == 3) ? P.n[DIR == 2 ? 1 : 2] : 1;
   const dim3 grid((na + TL - 1) / TL, (np + TP - 1) / TP, no);
-  hipLaunchKernelGGL((k_tvjp<ND, DIR, TT>), grid, dim3(TV_NT), 0, s, P, y, lam, scale, out);
+  hipLaunchKernelGGL((k_tvjp<ND, DIR, TT>), grid, dim3(TV_NT), 0, s, P, y, lam, scale, out,
+                     accumulate ? 1 : 0);
 }
 
+// out (rows E, F) = scale s'(y)^T lam, added to what out holds when accumulate,
+// else written over it: the x launch sets or adds, y and z add
 template <int ND, typename TT>
 static hipError_t transport_vjp_t(const DevParams& P, const double* y, const double* lam,
-                                  double scale, double* out, hipStream_t s) {
-  launch_tvjp<ND, 0, TT>(P, y, lam, scale, out, s);
-  if constexpr (ND >= 2) launch_tvjp<ND, 1, TT>(P, y, lam, scale, out, s);
-  if constexpr (ND >= 3) launch_tvjp<ND, 2, TT>(P, y, lam, scale, out, s);
+                                  double scale, double* out, bool accumulate, hipStream_t s) {
+  launch_tvjp<ND, 0, TT>(P, y, lam, scale, out, accumulate, s);
+  if constexpr (ND >= 2) launch_tvjp<ND, 1, TT>(P, y, lam, scale, out, true, s);
+  if constexpr (ND >= 3) launch_tvjp<ND, 2, TT>(P, y, lam, scale, out, true, s);
   return hipGetLastError();
 }
 
 // float32 stencil for a mixed-precision handle, double otherwise
 template <int ND>
 static hipError_t transport_vjp(const DevParams& P, bool mixed, const double* y, const double* lam,
-                                double scale, double* out, hipStream_t s) {
-  return mixed ? transport_vjp_t<ND, float>(P, y, lam, scale, out, s)
-               : transport_vjp_t<ND, double>(P, y, lam, scale, out, s);
+                                double scale, double* out, bool accumulate, hipStream_t s) {
+  return mixed ? transport_vjp_t<ND, float>(P, y, lam, scale, out, accumulate, s)
+               : transport_vjp_t<ND, double>(P, y, lam, scale, out, accumulate, s);
 }
 
 template <int ND>
@@ -791,15 +794,17 @@ static hipError_t adjoint_nd(const AdjointArgs& A) {
   const unsigned nbc = blocks_for(N);
   const double dt = A.dt;
   for (int n = A.nsteps - 1; n >= 0; --n) {
-    // stage 2 source at y^{n+1}: mu2 in Lc, La = mu2/2
-    hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, Y(n + 1), Lc, A.rho,
-                       A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF, La, 0.5, nullptr, 0.0, nullptr, 0.0);
-    e = transport_vjp<ND>(P, A.mixed, H(n), Lc, 0.5 * dt, La, s);
+    // stage 2 source at y^{n+1}: mu2 into Lc (in place)
+    hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, Y(n + 1), Lc, 1.0,
+                       nullptr, Lc, A.rho, A.kP, A.kF, 0.5 * dt, A.gkP, A.gkF, nullptr, 0.0);
+    // its transport: La (rows E, F) = dt/2 s'(y^{n+1/2})^T mu2
+    e = transport_vjp<ND>(P, A.mixed, H(n), Lc, 0.5 * dt, La, false, s);
     if (e != hipSuccess) return e;
-    // stage 1 source at y^{n+1/2}: mu1 in La, Ln = mu1 + mu2/2 (mu2 still in Lc)
-    hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, H(n), La, A.rho, A.kP,
-                       A.kF, dt, A.gkP, A.gkF, nullptr, 0.0, Ln, 1.0, Lc, 0.5);
-    e = transport_vjp<ND>(P, A.mixed, Y(n), La, dt, Ln, s);
+    // stage 1 source at y^{n+1/2} with lambda = mu2/2 + La: mu1 into La, and
+    // Ln = mu1 + mu2/2 (mu2 still in Lc)
+    hipLaunchKernelGGL((k_src_adj<ND>), dim3(nbc), dim3(ATHREADS), 0, s, P, H(n), Lc, 0.5, La, La,
+                       A.rho, A.kP, A.kF, dt, A.gkP, A.gkF, Ln, 0.5);
+    e = transport_vjp<ND>(P, A.mixed, Y(n), La, dt, Ln, true, s);
     if (e != hipSuccess) return e;
     double* t = Lc;
     Lc = Ln;
