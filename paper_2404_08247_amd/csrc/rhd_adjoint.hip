@@ -775,22 +775,24 @@ static hipError_t adjoint_nd(const AdjointArgs& A) {
   const long long M = (long long)nv * N;
   hipStream_t s = A.stream;
   hipError_t e;
-  auto Y = [&](int n) { return A.states + (long long)n * M; };                 // y^n, n = 0..k
-  auto H = [&](int n) { return A.states + (long long)(A.nsteps + 1 + n) * M; }; // y^{n+1/2}
+  // y^0 is the caller's state0 (read only); y^1..y^k and y^{1/2}..y^{k-1/2} are
+  // written into the workspace
+  auto Yw = [&](int n) { return A.states + (long long)(n - 1) * M; };          // y^n, n >= 1
+  auto Y = [&](int n) -> const double* { return n == 0 ? A.state0 : Yw(n); };
+  auto H = [&](int n) { return A.states + (long long)(A.nsteps + n) * M; };    // y^{n+1/2}
   // forward recompute of the segment
-  e = hipMemcpyAsync(Y(0), A.state0, M * sizeof(double), hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
   for (int n = 0; n < A.nsteps; ++n) {
     e = launch_stage(P, MODE_STAGE1, A.mixed, Y(n), Y(n), H(n), A.rho, A.kP, A.kF, A.dt, A.err, s);
     if (e != hipSuccess) return e;
-    e = launch_stage(P, MODE_STAGE2, A.mixed, H(n), Y(n), Y(n + 1), A.rho, A.kP, A.kF, A.dt, A.err, s);
+    e = launch_stage(P, MODE_STAGE2, A.mixed, H(n), Y(n), Yw(n + 1), A.rho, A.kP, A.kF, A.dt,
+                     A.err, s);
     if (e != hipSuccess) return e;
   }
-  double* Lc = A.lam_a;
+  // the adjoint runs in place in the caller's lambda and two workspace vectors;
+  // the swaps leave it in lambda after an even number of steps, else one copy
+  double* Lc = A.lambda;
   double* La = A.lam_b;
   double* Ln = A.lam_c;
-  e = hipMemcpyAsync(Lc, A.lambda, M * sizeof(double), hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
   const unsigned nbc = blocks_for(N);
   const double dt = A.dt;
   for (int n = A.nsteps - 1; n >= 0; --n) {
@@ -810,8 +812,10 @@ static hipError_t adjoint_nd(const AdjointArgs& A) {
     Lc = Ln;
     Ln = t;
   }
-  e = hipMemcpyAsync(A.lambda, Lc, M * sizeof(double), hipMemcpyDeviceToDevice, s);
-  if (e != hipSuccess) return e;
+  if (Lc != A.lambda) {
+    e = hipMemcpyAsync(A.lambda, Lc, M * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 

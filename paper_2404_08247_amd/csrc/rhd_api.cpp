@@ -111,11 +111,12 @@ Layout layout(const rhd_params* p, int adj_len) {
   off = align_up(off + (size_t)kPartialBlocks * 4 * sizeof(double));
   L.adj = off;
   if (adj_len > 0) {
-    // y^0..y^k and y^{1/2}..y^{k-1/2} of a segment, and three adjoint vectors
+    // y^1..y^k and y^{1/2}..y^{k-1/2} of a segment (y^0 is the caller's state0),
+    // and two adjoint vectors (the third is the caller's lambda)
     L.states = off;
-    off = align_up(off + (size_t)(2 * adj_len + 1) * nv * N * sizeof(double));
+    off = align_up(off + (size_t)(2 * adj_len) * nv * N * sizeof(double));
     L.lam = off;
-    off = align_up(off + 3 * nv * N * sizeof(double));
+    off = align_up(off + 2 * nv * N * sizeof(double));
   }
   L.total = off;
   return L;
@@ -552,9 +553,8 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
   A.kP = h->kP;
   A.kF = h->kF;
   A.states = h->adj.states;
-  A.lam_a = h->adj.lam;
-  A.lam_b = h->adj.lam + M;
-  A.lam_c = h->adj.lam + 2 * M;
+  A.lam_b = h->adj.lam;
+  A.lam_c = h->adj.lam + M;
   A.err = h->err;
   A.stream = h->stream;
   e = rhd::launch_adjoint(A);

@@ -80,9 +80,8 @@ struct AdjointArgs {
   const double* rho;
   const double* kP;
   const double* kF;
-  double* states;         // (2 nsteps + 1) states: y^0..y^k, then y^{1/2}..y^{k-1/2}
-  double* lam_a;
-  double* lam_b;
+  double* states;         // 2 nsteps states: y^1..y^k, then y^{1/2}..y^{k-1/2}
+  double* lam_b;          // two adjoint vectors of nvar N doubles
   double* lam_c;
   unsigned long long* err;
   hipStream_t stream;
