@@ -47,7 +47,7 @@ HEADLINE = "3-D 256^3 dynamic diffusion, periodic, v = 0.01 c, chat = c/50, 300 
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("rhd_forward.hip", "rhd_device.hpp", "rhd_internal.hpp"):
+    for f in ("rhd_stage.hpp", "rhd_forward.hip", "rhd_device.hpp", "rhd_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2404_08247_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librhd.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["rhd_forward.hip", "rhd_adjoint.hip", "rhd_hydro.hip", "rhd_api.cpp"]
+SOURCES = ["rhd_forward.hip", "rhd_stage2d.hip", "rhd_adjoint.hip", "rhd_hydro.hip", "rhd_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -23,9 +23,11 @@ FLAGS = [
 ]
 
 
-# Per-file device-compiler options: the stage kernels schedule for ILP (measured
-# 1.3 % faster on the 128^3 FP64 step than the default occupancy-driven scheduler,
-# with bitwise-identical results).
+# Per-file device-compiler options: the 1-D and 3-D stage kernels schedule for ILP
+# (measured 1.9 % faster on the 256^3 FP64 step than the default occupancy-driven
+# scheduler, with bitwise-identical results); the 2-D ones (rhd_stage2d.hip) keep
+# the default scheduler, under which their four-wave build needs no spills (3-5 %
+# faster on the 512^2 step than max-ILP with spills).
 FILE_FLAGS = {"rhd_forward.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]}
 
 

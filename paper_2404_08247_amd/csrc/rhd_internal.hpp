@@ -48,6 +48,10 @@ enum BoundaryKind : int { BC_PERIODIC = 0, BC_REFLECT = 1, BC_INFLOW = 2 };
 hipError_t launch_stage(const DevParams& P, int mode, bool mixed, const double* ysten,
                         const double* yown, double* yout, const double* rho, const double* kP,
                         const double* kF, double dt, unsigned long long* err, hipStream_t s);
+// launch_stage for a 2-D grid (rhd_stage2d.hip)
+hipError_t launch_stage_2d(const DevParams& P, int mode, bool mixed, const double* ysten,
+                           const double* yown, double* yout, const double* rho, const double* kP,
+                           const double* kF, double dt, unsigned long long* err, hipStream_t s);
 // 1-D grids of at most 510 cells without the eps correction: whole steps in one
 // single-workgroup launch (rhd_forward.hip)
 bool line_kernel_applies(const DevParams& P);
