@@ -138,7 +138,10 @@ rhd_status rhd_step(rhd_handle* h, double* state, double dt, int32_t nsteps);
 /* Reverse-mode derivative of nsteps steps (1 <= nsteps <= the segment length
  * that the handle's workspace holds, see rhd_create) started from state0
  * (device, not modified).
- *   lambda: in: dJ/dy at the end of the segment; out: dJ/dy at its start.
+ *   lambda: in: dJ/dy at the end of the segment; out: dJ/dy at its start. The
+ *     reversal runs in this array (working storage during the call; on an error
+ *     return its contents are unspecified). state0 is read until the call ends
+ *     and must not overlap lambda or the gradient arrays.
  *   g_kappa_P, g_kappa_F: device [nz][ny][nx]; dJ/dkappa is ADDED (+=). With
  *     kappa_F aliasing kappa_P, g_kappa_F may be NULL and both contributions go
  *     into g_kappa_P.
