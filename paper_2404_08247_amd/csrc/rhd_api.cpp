@@ -525,7 +525,17 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
   if (!state0 || !lambda || !g_kappa_P || misaligned(state0) || misaligned(lambda) ||
       misaligned(g_kappa_P) || misaligned(g_kappa_F) || !std::isfinite(dt) || !(dt > 0.0))
     return set_err(h, RHD_EINVAL, -1, "invalid state0, lambda, g_kappa_P, g_kappa_F or dt");
-  if (state0 == lambda) return set_err(h, RHD_EINVAL, -1, "state0 and lambda must not alias");
+  {
+    // the reversal runs in lambda and reads state0 until it ends: no overlaps
+    const size_t nst = (size_t)nvar_of(&h->p) * (size_t)h->dp.N, nf = (size_t)h->dp.N;
+    auto overlap = [](const double* a, size_t na, const double* b, size_t nb) {
+      return b && a < b + nb && b < a + na;
+    };
+    if (overlap(state0, nst, lambda, nst) || overlap(state0, nst, g_kappa_P, nf) ||
+        overlap(state0, nst, g_kappa_F, nf) || overlap(lambda, nst, g_kappa_P, nf) ||
+        overlap(lambda, nst, g_kappa_F, nf))
+      return set_err(h, RHD_EINVAL, -1, "state0, lambda and the gradient arrays must not overlap");
+  }
   if (!h->dp.kF_alias && !g_kappa_F)
     return set_err(h, RHD_EINVAL, -1, "a separate kappa_F needs g_kappa_F");
   if (h->p.scheme != RHD_SCHEME_PDARS)

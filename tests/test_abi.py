@@ -161,6 +161,37 @@ def test_adjoint_segment_capacity_follows_the_workspace_size():
             L.rhd_destroy(h)
 
 
+def test_adjoint_rejects_overlapping_arrays_before_touching_the_gpu():
+    """rhd_step_adjoint reverses in lambda and reads state0 until it returns, so
+    overlapping state0, lambda and gradient arrays are rejected with RHD_EINVAL
+    before any HIP call (fake device addresses: this runs without a GPU)."""
+    from paper_2404_08247_amd import rhd
+    L = rhd.lib
+    fake = ctypes.c_void_p(1 << 20)
+    w = W.config4(n=(16, 12))
+    rp = rhd.make_params(w.params)
+    nb = L.rhd_workspace_bytes(ctypes.byref(rp), 2)
+    h = ctypes.c_void_p()
+    assert L.rhd_create(ctypes.byref(rp), fake, fake, None, fake, nb, None, ctypes.byref(h)) == 0
+    nst = w.nvar * 16 * 12 * 8          # bytes of one state
+    base = 1 << 30
+    cases = [
+        (base, base + 8 * 7, base + 4 * nst),                 # lambda starts inside state0
+        (base + nst - 8, base, base + 4 * nst),               # state0 ends inside lambda
+        (base, base + 2 * nst, base + 3 * nst - 64),          # g_kappa_P overlaps lambda's end
+        (base, base + 2 * nst, base + 64),                    # g_kappa_P inside state0
+    ]
+    msg = ctypes.create_string_buffer(256)
+    cell = ctypes.c_int64(0)
+    for s0, lam, gk in cases:
+        st = L.rhd_step_adjoint(h, ctypes.c_void_p(s0), ctypes.c_double(0.1), 1,
+                                ctypes.c_void_p(lam), ctypes.c_void_p(gk), None)
+        assert st == -1, (s0, lam, gk)
+        L.rhd_last_error(h, ctypes.byref(cell), msg, 256)
+        assert b"overlap" in msg.value
+    L.rhd_destroy(h)
+
+
 def test_noalloc_step_validates_before_touching_the_gpu():
     """rhd_step_noalloc rejects invalid parameters, pointers and dt with RHD_EINVAL
     and a grid whose y^{n+1/2} does not fit its 64 MiB static scratch with
