@@ -74,3 +74,13 @@ def test_noalloc_step_reports_failures_like_rhd_step(torch_dev, orc):
     got, gcell = rhd.step_noalloc(w.params, y, _to(torch_dev, w.rho), _to(torch_dev, w.kappa_P),
                                   None, w.dt, 1)
     assert got == rhd.RHD_ENEWTON and gcell == cell, (got, gcell, cell)
+
+
+def test_noalloc_step_at_the_largest_grid_its_scratch_holds(torch_dev):
+    # 256 + 8 nvar N <= 64 MiB: 128 x 128 x 63 = 1032192 cells in 3-D (64 planes,
+    # 1048576 cells, would need 256 bytes more than the scratch holds and are
+    # rejected, as the CPU test of the validation checks)
+    w = W.config2(n=(128, 128, 63), nsteps=2)
+    assert 256 + 8 * w.nvar * w.ncells <= 64 << 20 < 256 + 8 * w.nvar * 128 * 128 * 64
+    _say("noalloc largest grid", w.n, w.nsteps)
+    _compare(torch_dev, w, 1e-10)
