@@ -213,3 +213,23 @@ def test_noalloc_step_validates_before_touching_the_gpu():
     assert L.rhd_step_noalloc(*args(big, fake, 0.1)) == -5
     # a grid that fits gets past the size check (and then needs a GPU)
     assert L.rhd_step_noalloc(*args(fits, fake, 0.1)) != -5
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """The product path has no fallback: importing the binding from a copy of the
+    package that lacks librhd.so raises ImportError naming the missing file."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_2404_08247_amd")
+    dst = tmp_path / "paper_2404_08247_amd"
+    dst.mkdir()
+    for f in os.listdir(src):
+        if f.endswith(".py"):
+            shutil.copy(os.path.join(src, f), dst / f)
+    code = ("import sys; sys.path.insert(0, sys.argv[1])\n"
+            "try:\n    import paper_2404_08247_amd.rhd\nexcept ImportError as e:\n"
+            "    print('IMPORTERROR', e); sys.exit(3)\nprint('IMPORTED'); sys.exit(0)\n")
+    r = subprocess.run([sys.executable, "-c", code, str(tmp_path)], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 3 and "librhd.so is missing" in r.stdout, (r.returncode, r.stdout, r.stderr)
