@@ -47,7 +47,7 @@ constexpr int stage_waves() { return (ND == 2 && VAR == 0) ? 4 : RHD_STAGE_WAVES
 #define RHD_TX 32
 #endif
 #ifndef RHD_ZCHUNK_MAX
-#define RHD_ZCHUNK_MAX 64
+#define RHD_ZCHUNK_MAX 128
 #endif
 #ifndef RHD_STAGE_SLOTS
 #define RHD_STAGE_SLOTS 512
