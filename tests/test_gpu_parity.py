@@ -458,6 +458,8 @@ LINE_CASES = {
     "c1_rk2ssp_order1": lambda: W.config1(n=128, nsteps=60, scheme="rk2ssp", v_order=1),
     "marshak_cfl10": lambda: W.marshak(cfl=10.0, t_end=2e-9),
     "one_cell": lambda: W.config1(n=1, nsteps=20, bc=(0,)),
+    "two_cells_periodic": lambda: W.config1(n=2, nsteps=20, bc=(0,)),
+    "three_cells_reflect": lambda: W.config1(n=3, nsteps=20),
     "widest_line": lambda: W.config1(n=510, nsteps=30),
     "one_past_widest": lambda: W.config1(n=511, nsteps=30),
 }
@@ -473,7 +475,7 @@ def test_single_workgroup_line_steps_match_two_kernel_path(torch_dev, orc, case)
     _say("line kernel", case, w.n, w.nsteps, w.params.get("precision"))
     rng = np.random.default_rng(5)
     y0 = w.y0.copy()
-    if case.startswith("c1"):
+    if case.startswith(("c1", "two", "three")):
         y0[1] = 0.3 * w.params["c"] * y0[0] * rng.uniform(-1, 1, y0[0].shape)
     S = _solver(torch_dev, w)
     a = _to(torch_dev, y0)
