@@ -531,6 +531,38 @@ def test_gpu_steps_are_bitwise_deterministic(torch_dev):
     assert np.array_equal(outs[0], outs[1])
 
 
+def test_a_handle_on_a_side_stream_gives_the_same_steps(torch_dev):
+    """A handle binds the stream that is current when it is created and enqueues
+    every kernel there (the error-word read included). On a second stream of
+    default priority the steps, the adjoint and the totals equal those of a
+    handle on the default stream bitwise."""
+    from paper_2404_08247_amd import rhd
+    torch, dev = torch_dev
+    w = W.config5(n=(36, 20, 18), nsteps=3, precision="fp64")
+    rho, kap = _to(torch_dev, w.rho), _to(torch_dev, w.kappa_P)
+    out = []
+    side = torch.cuda.Stream(device=dev)            # default priority
+    for stream in (None, side):
+        ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(None)
+        if stream is not None:
+            stream.wait_stream(torch.cuda.default_stream(dev))
+        with ctx:
+            S = rhd.Solver(w.params, rho, kap, None, w.nsteps, dev)
+            y = _to(torch_dev, w.y0)
+            y0 = y.clone()
+            S.step(y, w.dt, w.nsteps)
+            tot = S.conserved_totals(y)
+            lam = torch.ones_like(y)
+            gk = torch.zeros_like(kap)
+            S.step_adjoint(y0, w.dt, w.nsteps, lam, gk)
+        torch.cuda.synchronize()
+        out.append((y.cpu().numpy(), tot, lam.cpu().numpy(), gk.cpu().numpy()))
+        _say("  stream", "side" if stream is not None else "default", "totals", tot)
+    (ya, ta, la, ga), (yb, tb, lb, gb) = out
+    assert np.array_equal(ya, yb) and ta == tb
+    assert np.array_equal(la, lb) and np.array_equal(ga, gb)
+
+
 def test_gpu_translation_invariance(torch_dev):
     w = W.config2(n=(40, 20, 16), nsteps=2)
     shift = (3, -5, 7)
