@@ -165,8 +165,8 @@ rhd_status rhd_source(rhd_handle* h, double* y, double tau);
 rhd_status rhd_stage1(rhd_handle* h, const double* y, double* yh, double dt);
 
 /* rhd_step without a handle or workspace, for callers that cannot allocate
- * device memory (code under graph capture, tight serving loops, harnesses that
- * forbid hipMalloc). It allocates nothing: y^{n+1/2} and the error word live in
+ * device memory (tight serving loops, harnesses that forbid hipMalloc). It
+ * allocates nothing: y^{n+1/2} and the error word live in
  * a static device array of 64 MiB that the library holds on every GPU it runs
  * on until the process ends. Arguments as for rhd_create and rhd_step (device
  * pointers; kappa_F NULL for kappa_F = kappa_P; hip_stream NULL = default
@@ -176,7 +176,9 @@ rhd_status rhd_stage1(rhd_handle* h, const double* y, double* yh, double dt);
  * 2.1e6 in 1-D); larger grids return RHD_EWORKSPACE before any launch. The
  * static array is shared by every call on that GPU and keeps the last call's
  * contents, so calls that overlap on one GPU (other streams or threads) race.
- * The optional kappa_E and S fields of a handle are not available here.
+ * The optional kappa_E and S fields of a handle are not available here. Like
+ * rhd_step it ends by reading the error word back and synchronizing the stream,
+ * so it cannot be recorded into a HIP graph.
  * Returns the statuses of rhd_step (RHD_EINVAL for invalid parameters or
  * pointers, with nothing launched). */
 rhd_status rhd_step_noalloc(const rhd_params* p, const double* rho, const double* kappa_P,
