@@ -529,7 +529,8 @@ rhd_status rhd_step_adjoint(rhd_handle* h, const double* state0, double dt, int3
     // the reversal runs in lambda and reads state0 until it ends: no overlaps
     const size_t nst = (size_t)nvar_of(&h->p) * (size_t)h->dp.N, nf = (size_t)h->dp.N;
     auto overlap = [](const double* a, size_t na, const double* b, size_t nb) {
-      return b && a < b + nb && b < a + na;
+      const uintptr_t ua = reinterpret_cast<uintptr_t>(a), ub = reinterpret_cast<uintptr_t>(b);
+      return b && ua < ub + nb * sizeof(double) && ub < ua + na * sizeof(double);
     };
     if (overlap(state0, nst, lambda, nst) || overlap(state0, nst, g_kappa_P, nf) ||
         overlap(state0, nst, g_kappa_F, nf) || overlap(lambda, nst, g_kappa_P, nf) ||
