@@ -37,12 +37,6 @@ constexpr int NTHREADS = 256;
 #ifndef RHD_STAGE_WAVES
 #define RHD_STAGE_WAVES 1
 #endif
-// The plain 2-D kernels fit 128 VGPRs without spills: four waves per SIMD, so
-// with their 39 KB of LDS four workgroups share a CU and a 512^2 grid (1024
-// tiles) runs in one round instead of two.
-template <int ND, int VAR>
-constexpr int stage_waves() { return (ND == 2 && VAR == 0) ? 4 : RHD_STAGE_WAVES; }
-
 #ifndef RHD_TX
 #define RHD_TX 32
 #endif
@@ -76,6 +70,13 @@ __device__ __forceinline__ double inflow_value(const DevParams& P, int r, int ax
 // opacities; VAR_EPS, the optional Skinner-type eps on the HLL energy flux, which
 // stages chi_F = rho kappa_F of the tile in LDS, with the general source.
 enum { VAR_PLAIN = 0, VAR_EPS = 1, VAR_GEN = 2, VAR_TDEP = 3 };
+
+// The plain 2-D kernels fit 128 VGPRs without spills (under the default
+// scheduler, which their file uses): four waves per SIMD, so with their 39 KB of
+// LDS four workgroups share a CU and a 512^2 grid (1024 tiles) runs in one round
+// instead of two. The other variants keep RHD_STAGE_WAVES.
+template <int ND, int VAR>
+constexpr int stage_waves() { return (ND == 2 && VAR == VAR_PLAIN) ? 4 : RHD_STAGE_WAVES; }
 
 template <int ND, int MODE, typename TT, int VAR>
 __global__ void __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(stage_waves<ND, VAR>())))
