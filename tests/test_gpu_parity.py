@@ -295,6 +295,7 @@ STEP_CASES = {
                                              hll_eps_cells=2.0), MIXED_TOL),
     "c2_thin_axes": (lambda: W.config2(n=(20, 2, 1), nsteps=5), FP64_TOL),
     "c4_small_mixed": (lambda: W.config4(n=(72, 40), nsteps=10, precision="mixed"), MIXED_TOL),
+    "c4_full_512sq_20_steps": (lambda: W.config4(nsteps=20), FP64_TOL),   # every cell compared
     "c4_small_reflect": (lambda: W.config4(n=(72, 40), nsteps=10, bc=(1, 1)), FP64_TOL),
     "c3_small_eddington": (lambda: W.config3(n=(48, 24, 20), nsteps=8, precision="fp64",
                                              closure="eddington"), FP64_TOL),
