@@ -363,29 +363,42 @@ def _subbox_oracle(orc, w, y, corner, m, nsteps=1):
     return out[:, halo:halo + m, halo:halo + m, halo:halo + m]
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c3_fp64", "c3_mixed", "c5_fp64", "c5_mixed"])
+@pytest.mark.parametrize("cfg", ["c2", "c3_fp64", "c3_mixed", "c5_fp64", "c5_mixed",
+                                 "c3_fp64_4_steps", "c3_mixed_4_steps"])
 def test_full_size_one_step_sampled(torch_dev, orc, cfg):
     mk = {"c2": lambda: W.config2(),
           "c3_fp64": lambda: W.config3(precision="fp64"),
           "c3_mixed": lambda: W.config3(precision="mixed"),
           "c5_fp64": lambda: W.config5(precision="fp64"),
-          "c5_mixed": lambda: W.config5(precision="mixed")}[cfg]
+          "c5_mixed": lambda: W.config5(precision="mixed"),
+          "c3_fp64_4_steps": lambda: W.config3(precision="fp64"),
+          "c3_mixed_4_steps": lambda: W.config3(precision="mixed")}[cfg]
+    nsteps = 4 if cfg.endswith("4_steps") else 1
     w = mk()
-    _say("full-size sampled", cfg, w.n)
+    _say("full-size sampled", cfg, w.n, nsteps)
     S = _solver(torch_dev, w)
     yd = _to(torch_dev, w.y0)
-    S.step(yd, w.dt, 1)
+    S.step(yd, w.dt, nsteps)
     got = yd.cpu().numpy()
     tol = FP64_TOL if w.params["precision"] == "fp64" else MIXED_TOL
     rng = np.random.default_rng(1)
     m = 12
     nx, ny, nz = w.n
+    # L-inf error per field relative to that field's largest magnitude over the whole
+    # grid, as in the other step tests (the oracle runs on sub-boxes only, so the
+    # scale comes from the GPU field, which equals the oracle's to the bar); a
+    # sub-box's own maximum can be orders of magnitude smaller where a field is
+    # nearly zero (the transverse fluxes far from the pulse)
+    scale = np.abs(got).reshape(w.nvar, -1).max(axis=1)
     for trial in range(3):
         corner = (int(rng.integers(0, nz)), int(rng.integers(0, ny)), int(rng.integers(0, nx)))
-        ref = _subbox_oracle(orc, w, w.y0, corner, m)
+        ref = _subbox_oracle(orc, w, w.y0, corner, m, nsteps)
         idx = [(np.arange(m) + c0) % n for c0, n in zip(corner, (nz, ny, nx))]
         g = got[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]
-        err = _rel_err(g, ref, range(w.nvar))
+        err = np.array([np.abs(g[v] - ref[v]).max() / scale[v] if scale[v] > 0
+                        else np.abs(g[v] - ref[v]).max() for v in range(w.nvar)])
+        local = _rel_err(g, ref, range(w.nvar))
+        _say("  corner", corner, "max err / grid max", err.max(), " / sub-box max", local.max())
         assert err.max() < tol, (corner, err)
 
 
